@@ -1,0 +1,304 @@
+"""Seeded synthetic inputs: hexahedral box meshes and initial states.
+
+This module holds no arithmetic of the flux-reconstruction method itself. It only builds
+the inputs that both the HIP library and the CPU oracle consume:
+
+* mesh descriptions (corner vertex ids in VTK hexahedron order plus geometry nodes at the
+  tensor Gauss-Lobatto-Legendre points of degree q, xi fastest),
+* an optional smooth curving of the node coordinates,
+* closed-form flow states (Taylor-Green vortex, isentropic vortex, uniform freestream)
+  evaluated at caller-supplied physical coordinates.
+
+The paper (section "FR Algorithm") states the method on unstructured hexahedra; its own
+workloads (a turbine cascade and a cooled vane) are not available, so periodic boxes with
+these closed-form states stand in for them.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# VTK hexahedron corner order: corner c sits at reference corner (bx, by, bz) in {0,1}^3.
+VTK_CORNERS = np.array(
+    [[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]],
+    dtype=np.int64,
+)
+
+GAMMA = 1.4
+PRANDTL = 0.72
+
+
+@dataclasses.dataclass
+class Mesh:
+    """A hexahedral mesh description.
+
+    elem_vert  : int64 [E, 8], corner vertex ids in VTK order. Periodic images share one id.
+    elem_nodes : float64 [E, (q+1)^3, 3], node coordinates at tensor GLL points of degree q,
+                 reference index i + (q+1)*(j + (q+1)*k) (xi fastest).
+    q          : geometry degree (>= 1).
+    shape      : (nx, ny, nz) for box meshes, informational.
+    lo, hi     : box corners, informational.
+    """
+
+    elem_vert: np.ndarray
+    elem_nodes: np.ndarray
+    q: int
+    shape: tuple = ()
+    lo: tuple = ()
+    hi: tuple = ()
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.elem_vert.shape[0])
+
+
+def gll_points(q: int) -> np.ndarray:
+    """Gauss-Lobatto-Legendre points of degree q (q+1 points, ascending) via numpy."""
+    if q < 1:
+        raise ValueError("GLL needs q >= 1")
+    inner = np.polynomial.legendre.Legendre.basis(q).deriv().roots()
+    return np.concatenate([[-1.0], np.sort(np.real(inner)), [1.0]])
+
+
+def curve_map(x: np.ndarray, amp: float, lo, hi, mode: str = "same") -> np.ndarray:
+    """Smooth curving of node coordinates.
+
+    mode "same" (the curved-mesh workload): every coordinate gets the same displacement
+    amp*L*sin(2 pi xh) sin(2 pi yh) sin(2 pi zh), xh = (x - lo)/L box-normalised, L the box
+    length along x. mode "mixed": the three coordinates get different displacements
+    (wavenumber 2 along x, y, z respectively for dx, dy, dz), which makes the cross-product
+    form of the metrics alias. Both vanish on the box faces, so periodic faces still match.
+    """
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    L = hi - lo
+    xh = (x - lo) / L
+    s = [np.sin(2 * np.pi * xh[..., c]) for c in range(3)]
+    base = amp * L[0] * s[0] * s[1] * s[2]
+    if mode == "same":
+        return x + base[..., None]
+    out = x.copy()
+    for c in range(3):
+        out[..., c] += base * np.cos(2 * np.pi * xh[..., c]) * 2.0
+    return out
+
+
+def box_mesh(n, lo=(0.0, 0.0, 0.0), hi=None, q: int = 1, periodic=(True, True, True),
+             curve_amp: float = 0.0, curve_mode: str = "same") -> Mesh:
+    """Uniform nx*ny*nz hexahedral box, optionally curved by `curve_map`.
+
+    Element (ie, je, ke) has index ie + nx*(je + ny*ke). In a periodic direction the vertex
+    lattice index wraps modulo n, so periodic images share a vertex id. At least 3 elements
+    are needed across a periodic direction: with 2, the sorted corner ids of distinct faces
+    coincide and the faces cannot be paired from vertex ids alone.
+    """
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+    if hi is None:
+        hi = (2 * np.pi, 2 * np.pi, 2 * np.pi)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    for nd, per in zip((nx, ny, nz), periodic):
+        if per and nd < 3:
+            raise ValueError("a periodic direction needs at least 3 elements")
+    vx = nx if periodic[0] else nx + 1
+    vy = ny if periodic[1] else ny + 1
+    vz = nz if periodic[2] else nz + 1
+
+    ie, je, ke = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ie = ie.transpose(2, 1, 0).reshape(-1)  # element index ie fastest
+    je = je.transpose(2, 1, 0).reshape(-1)
+    ke = ke.transpose(2, 1, 0).reshape(-1)
+    E = nx * ny * nz
+
+    cx = (ie[:, None] + VTK_CORNERS[None, :, 0]) % vx
+    cy = (je[:, None] + VTK_CORNERS[None, :, 1]) % vy
+    cz = (ke[:, None] + VTK_CORNERS[None, :, 2]) % vz
+    elem_vert = (cx + vx * (cy + vy * cz)).astype(np.int64)
+
+    r = (gll_points(q) + 1.0) / 2.0  # [0,1]
+    h = (hi - lo) / np.array([nx, ny, nz], dtype=np.float64)
+    # node (a, b, c) of element -> physical point, a fastest
+    ra, rb, rc = np.meshgrid(r, r, r, indexing="ij")
+    ra = ra.transpose(2, 1, 0).reshape(-1)
+    rb = rb.transpose(2, 1, 0).reshape(-1)
+    rc = rc.transpose(2, 1, 0).reshape(-1)
+    nodes = np.empty((E, (q + 1) ** 3, 3), dtype=np.float64)
+    nodes[:, :, 0] = lo[0] + h[0] * (ie[:, None] + ra[None, :])
+    nodes[:, :, 1] = lo[1] + h[1] * (je[:, None] + rb[None, :])
+    nodes[:, :, 2] = lo[2] + h[2] * (ke[:, None] + rc[None, :])
+    if curve_amp != 0.0:
+        nodes = curve_map(nodes, curve_amp, lo, hi, curve_mode)
+    return Mesh(elem_vert=elem_vert, elem_nodes=np.ascontiguousarray(nodes), q=q,
+                shape=(nx, ny, nz), lo=tuple(lo), hi=tuple(hi))
+
+
+# ---------------------------------------------------------------------------------------------
+# Closed-form states. xyz has shape [..., 3]; the result has shape [..., 5] holding the
+# conserved variables (rho, rho u, rho v, rho w, E).
+# ---------------------------------------------------------------------------------------------
+
+def _conserved(rho, u, v, w, p, gamma=GAMMA):
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E], axis=-1)
+
+
+def tgv_state(xyz: np.ndarray, mach: float = 0.1, gamma: float = GAMMA) -> np.ndarray:
+    """Taylor-Green vortex initial condition on [0, 2 pi)^3 with unit length, speed, density.
+
+    u = sin x cos y cos z, v = -cos x sin y cos z, w = 0,
+    p = p0 + (cos 2x + cos 2y)(cos 2z + 2)/16 with p0 = 1/(gamma Ma^2), rho = p/p0.
+    """
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    p0 = 1.0 / (gamma * mach * mach)
+    u = np.sin(x) * np.cos(y) * np.cos(z)
+    v = -np.cos(x) * np.sin(y) * np.cos(z)
+    w = np.zeros_like(u)
+    p = p0 + (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0) / 16.0
+    rho = p / p0
+    return _conserved(rho, u, v, w, p, gamma)
+
+
+def vortex_state(xyz: np.ndarray, t: float = 0.0, beta: float = 5.0, center=(0.0, 0.0),
+                 uinf=(1.0, 0.0), gamma: float = GAMMA, period=None) -> np.ndarray:
+    """Isentropic vortex (an exact Euler solution advected with speed uinf).
+
+    T = 1 - (gamma-1) beta^2/(8 gamma pi^2) exp(1 - r^2), rho = T^(1/(gamma-1)), p = rho T,
+    du = -(beta/2pi)(y-yc) exp((1-r^2)/2), dv = (beta/2pi)(x-xc) exp((1-r^2)/2), w = 0.
+    r is measured from the advected centre; with `period=(Lx, Ly)` the nearest periodic image
+    of the centre is used.
+    """
+    x, y = xyz[..., 0], xyz[..., 1]
+    xc = center[0] + uinf[0] * t
+    yc = center[1] + uinf[1] * t
+    dx = x - xc
+    dy = y - yc
+    if period is not None:
+        dx = dx - period[0] * np.round(dx / period[0])
+        dy = dy - period[1] * np.round(dy / period[1])
+    r2 = dx * dx + dy * dy
+    f = np.exp(0.5 * (1.0 - r2))
+    u = uinf[0] - beta / (2 * np.pi) * dy * f
+    v = uinf[1] + beta / (2 * np.pi) * dx * f
+    w = np.zeros_like(u)
+    T = 1.0 - (gamma - 1.0) * beta * beta / (8.0 * gamma * np.pi * np.pi) * f * f
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    return _conserved(rho, u, v, w, p, gamma)
+
+
+def freestream_state(xyz: np.ndarray, mach: float = 0.1, direction=(1.0, 0.5, 0.25),
+                     gamma: float = GAMMA) -> np.ndarray:
+    """Uniform flow: rho = 1, p = 1/(gamma Ma^2), |u| = Ma*c along `direction` (so |u| = 1)."""
+    d = np.asarray(direction, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    p0 = 1.0 / (gamma * mach * mach)
+    c0 = math.sqrt(gamma * p0)
+    shape = xyz.shape[:-1]
+    rho = np.ones(shape)
+    vel = mach * c0 * d
+    return _conserved(rho, rho * vel[0], rho * vel[1], rho * vel[2], p0 * rho, gamma)
+
+
+def points_to_state_layout(Upts: np.ndarray) -> np.ndarray:
+    """[E, Ns, 5] -> [E, 5, Ns] (the library layout: points innermost)."""
+    return np.ascontiguousarray(np.transpose(Upts, (0, 2, 1)))
+
+
+def state_from_coords(xyz_e3s: np.ndarray, fn, **kw) -> np.ndarray:
+    """Evaluate a closed-form state at solution-point coordinates laid out [E, 3, Ns]."""
+    pts = np.transpose(xyz_e3s, (0, 2, 1))
+    return points_to_state_layout(fn(pts, **kw))
+
+
+def random_smooth_perturbation(xyz_e3s: np.ndarray, seed: int, amp: float = 1e-3,
+                               modes: int = 3, period=(2 * np.pi,) * 3) -> np.ndarray:
+    """A seeded smooth random field [E, 5, Ns]: a few low Fourier modes per variable."""
+    rng = np.random.default_rng(seed)
+    pts = np.transpose(xyz_e3s, (0, 2, 1))
+    out = np.zeros(pts.shape[:-1] + (5,))
+    k0 = 2 * np.pi / np.asarray(period)
+    for v in range(5):
+        for _ in range(modes):
+            k = rng.integers(1, 3, size=3) * k0
+            ph = rng.uniform(0, 2 * np.pi)
+            a = rng.normal()
+            out[..., v] += a * np.sin(pts @ k + ph)
+    return points_to_state_layout(amp * out)
+
+
+# ---------------------------------------------------------------------------------------------
+# Invariance scrambler: random element relabelling plus a random proper rotation of each
+# element's reference frame. The physical mesh and fields are unchanged; only their
+# description is permuted, which exercises every relative face orientation.
+# ---------------------------------------------------------------------------------------------
+
+def cube_rotations():
+    """The 24 proper rotations of the reference cube as signed permutation matrices."""
+    import itertools
+
+    mats = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            M = np.zeros((3, 3), dtype=np.int64)
+            for r in range(3):
+                M[r, perm[r]] = signs[r]
+            if round(np.linalg.det(M)) == 1:
+                mats.append(M)
+    return mats
+
+
+def _rotated_index_map(npts: int, M: np.ndarray) -> np.ndarray:
+    """For a symmetric tensor point set, new flat index -> old flat index under xi' = M xi."""
+    idx = np.arange(npts)
+    k, j, i = np.meshgrid(idx, idx, idx, indexing="ij")
+    new = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=0)  # flat index i fastest
+    c_new = 2 * new - (npts - 1)
+    c_old = M.T @ c_new
+    old = (c_old + (npts - 1)) // 2
+    return old[0] + npts * (old[1] + npts * old[2])
+
+
+def scramble_mesh(mesh: Mesh, seed: int):
+    """Return (new_mesh, info) with elements relabelled and each reference frame rotated.
+
+    info = (order, rot) where new element e' is old element order[e'] seen through rotation
+    matrix index rot[e'] of `cube_rotations()`.
+    """
+    rng = np.random.default_rng(seed)
+    E = mesh.n_elem
+    order = rng.permutation(E)
+    mats = cube_rotations()
+    rot = rng.integers(0, len(mats), size=E)
+    q = mesh.q
+    corner_lattice = {tuple(c): vi for vi, c in enumerate(VTK_CORNERS)}
+    ev = np.empty_like(mesh.elem_vert)
+    nodes = np.empty_like(mesh.elem_nodes)
+    for e_new in range(E):
+        e_old = order[e_new]
+        M = mats[rot[e_new]]
+        cmap = _rotated_index_map(2, M)
+        for c_new in range(8):
+            b = VTK_CORNERS[c_new]
+            old_flat = cmap[b[0] + 2 * (b[1] + 2 * b[2])]
+            ob = (old_flat % 2, (old_flat // 2) % 2, old_flat // 4)
+            ev[e_new, c_new] = mesh.elem_vert[e_old, corner_lattice[ob]]
+        nmap = _rotated_index_map(q + 1, M)
+        nodes[e_new] = mesh.elem_nodes[e_old][nmap]
+    new = Mesh(elem_vert=ev, elem_nodes=nodes, q=q, shape=mesh.shape, lo=mesh.lo, hi=mesh.hi)
+    return new, (order, rot)
+
+
+def scramble_field(X: np.ndarray, info, p: int) -> np.ndarray:
+    """Apply a mesh scramble to a per-solution-point field laid out [E, C, (p+1)^3]."""
+    order, rot = info
+    mats = cube_rotations()
+    out = np.empty_like(X)
+    maps = {}
+    for e_new in range(X.shape[0]):
+        r = int(rot[e_new])
+        if r not in maps:
+            maps[r] = _rotated_index_map(p + 1, mats[r])
+        out[e_new] = X[order[e_new]][:, maps[r]]
+    return out
