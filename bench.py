@@ -1,0 +1,184 @@
+"""Benchmark: DOF-updates/s per RK stage of the FR residual + low-storage RK stage on one MI355X.
+
+Default workload (the scaled-up plain-FR configuration): periodic 64^3 hexahedral box on
+[0, 2 pi)^3 whose nodes are curved by 0.05 L sin(2 pi x/L) sin(2 pi y/L) sin(2 pi z/L)
+(isoparametric, q = p = 3), Taylor-Green vortex at Mach 0.1 and Re 1600, Roe + BR2, the
+Carpenter-Kennedy five-stage RK45 with dt = 2.5e-4, FP64. One bench step is one full RK step
+(five stages); value = n_elem (p+1)^3 * stages / time.
+
+Prints one JSON line (rank 0) with the driver's fields plus `roofline` (dominant kernel, HBM
+bound, algorithmic bytes per launch over its mean launch time measured with HIP events on the
+launch stream) and `cpu_baseline` (the CPU oracle timed on a bounded element sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+STAGES = {"lsrk45": 5, "rk4": 4}
+
+
+def algorithmic_bytes(p: int, prec: str = "fp64"):
+    """Minimum HBM bytes per element per stage of the two-kernel design (state FP64).
+
+    pre-pass : read U (5 Ns) and volume geometry (10 Ns), write own face data (20 Nf)
+    element  : read U (5 Ns), volume geometry (10 Ns), neighbour face data (20 Nf), face geometry
+               (4 Nf), RK register dU (5 Ns); write dU (5 Ns) and U (5 Ns)
+    """
+    n = p + 1
+    Ns, Nf = n ** 3, 6 * n * n
+    w = 8 if prec == "fp64" else 4
+    k1 = 8 * 5 * Ns + w * (10 * Ns + 20 * Nf)
+    k3 = 8 * 15 * Ns + w * (10 * Ns + 24 * Nf)
+    return k1, k3
+
+
+def make_workload(n: int, p: int, curved: bool):
+    from paper_2308_06605_amd import inputs
+
+    mesh = inputs.box_mesh(n, q=p, curve_amp=0.05 if curved else 0.0)
+    return mesh
+
+
+def cpu_baseline(mesh, p, U, mu, flux, target_s=12.0):
+    """Time the CPU oracle's residual (one RK stage's work) on a bounded element sample."""
+    import oracle
+
+    threads = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        threads = min(threads, int(omp))
+    rng = np.random.default_rng(0)
+    E = mesh.n_elem
+    n_probe = min(E, 512)
+    probe = np.sort(rng.choice(E, size=n_probe, replace=False))
+    o = oracle.Oracle(mesh, p, mu=mu, flux=flux, active=probe, nthreads=threads)
+    o.residual(U)  # warm-up
+    t0 = time.perf_counter()
+    o.residual(U)
+    t_probe = time.perf_counter() - t0
+    n_sample = int(min(E, max(n_probe, n_probe * target_s / 3 / max(t_probe, 1e-6))))
+    sample = np.sort(rng.choice(E, size=n_sample, replace=False))
+    o = oracle.Oracle(mesh, p, mu=mu, flux=flux, active=sample, nthreads=threads)
+    o.residual(U)
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        o.residual(U)
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    dof = n_sample * (p + 1) ** 3
+    return {"value": dof / t, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"residual of {n_sample} random elements of the same mesh and state "
+                      f"(median of 3 after 1 warm-up), double precision, {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64, help="elements per direction")
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--affine", action="store_true", help="uncurved mesh")
+    ap.add_argument("--flux", default="roe")
+    ap.add_argument("--scheme", default="lsrk45")
+    ap.add_argument("--dt", type=float, default=2.5e-4)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2308_06605_amd import fr, inputs
+
+    torch.cuda.set_device(0)
+    mu = 1.0 / 1600.0
+    mesh = make_workload(args.n, args.p, not args.affine)
+    t0 = time.perf_counter()
+    g = fr.FRMesh(mesh, args.p, mu=mu, flux=args.flux)
+    t_setup = time.perf_counter() - t0
+    X = g.sol_coords()
+    U = inputs.state_from_coords(X, inputs.tgv_state)
+    g.set_state(U)
+    torch.cuda.synchronize()
+
+    stages = STAGES[args.scheme]
+    for _ in range(args.warmup):
+        g.rk_step(args.dt, args.scheme, 1)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    g.rk_step(args.dt, args.scheme, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    dof = mesh.n_elem * (args.p + 1) ** 3
+    value = dof * stages / (ms_step * 1e-3)
+
+    # per-kernel mean launch durations (HIP events on the launch stream)
+    k1_ms, k3_ms = g.profile_stages(args.dt, args.scheme, 2)
+    b1, b3 = algorithmic_bytes(args.p)
+    achieved = b3 * mesh.n_elem / (k3_ms * 1e-3) / 1e9
+    stage_bytes = (b1 + b3) * mesh.n_elem
+    ok = bool(np.isfinite(g.get_state()).all())
+
+    cpu = None
+    if not args.no_cpu:
+        try:
+            cpu = cpu_baseline(mesh, args.p, U, mu, args.flux)
+        except Exception as exc:  # report, never fake
+            cpu = {"error": str(exc)}
+
+    wl = (f"TGV Ma0.1 Re1600, {'curved' if not args.affine else 'affine'} periodic {args.n}^3 hex, "
+          f"p={args.p}, {args.flux.capitalize()}+BR2, {args.scheme.upper()} dt={args.dt}")
+    out = {
+        "metric": "DOF-updates/s per RK stage",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl, "n_elem": mesh.n_elem, "dof": dof, "p": args.p,
+                   "stages_per_step": stages, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_element (fused common flux + divergence + RK stage)",
+                     "bytes_per_launch": b3 * mesh.n_elem, "mean_launch_ms": k3_ms},
+        "stage": {"prepass_ms": k1_ms, "element_ms": k3_ms, "stage_ms": ms_step / stages,
+                  "stage_algorithmic_bytes": stage_bytes,
+                  "stage_hbm_frac": stage_bytes / (ms_step / stages * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+        "setup_s": t_setup,
+        "wall_s_timed": t_wall,
+        "finite": ok,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

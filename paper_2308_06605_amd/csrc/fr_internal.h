@@ -1,0 +1,108 @@
+// fr_internal.h -- library-private declarations shared by the host setup (fr_host.cpp) and the
+// HIP kernels (fr_kernels.hip). Not part of the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace frk {
+
+constexpr int kMaxP = 7;
+constexpr int kMaxN = kMaxP + 1;
+
+// 1-D operator tables of degree p on the Gauss-Legendre solution points, passed to kernels
+// by value (they live in the kernel-argument segment).
+struct Ops1D {
+  double D[kMaxN * kMaxN];  // D[a*n + b] = l_b'(x_a)
+  double lm[kMaxN];         // l_b(-1)
+  double lp[kMaxN];         // l_b(+1)
+  double gcL[kMaxN];        // correction from the face at xi = -1, multiplied by its sign -1:
+                            // the derivative of g_L at x_a
+  double gcR[kMaxN];        // derivative of g_R at x_a (face at xi = +1)
+};
+
+struct Ops1Df {
+  float D[kMaxN * kMaxN];
+  float lm[kMaxN];
+  float lp[kMaxN];
+  float gcL[kMaxN];
+  float gcR[kMaxN];
+};
+
+// Per element face: packed neighbour information.
+//   nbr   : neighbour element index
+//   code  : bits 0-2 neighbour's local face, bit 3 swap, bit 4 flip u, bit 5 flip v,
+//           bit 6 this side owns the face (its normal is the face's normal)
+// Point (a, b) of this face is point (u', v') of the neighbour's face with
+//   (u, v) = swap ? (b, a) : (a, b); u' = flip_u ? p - u : u; v' = flip_v ? p - v : v.
+struct FaceConn {
+  int32_t nbr;
+  int32_t code;
+};
+
+struct Physics {
+  double gamma;
+  double prandtl;
+  double mu;
+  double kappa;  // mu * gamma / (prandtl * (gamma - 1)): heat-flux coefficient on d(p/rho)
+};
+
+// RK stage parameters for the fused element kernel.
+enum StageMode : int32_t {
+  kModeResidual = 0,  // write R
+  kModeLSRK = 1,      // dU <- a dU + dt R; U <- U + b dU   (a == 0: dU is not read)
+  kModeRK4 = 2        // acc <- (first ? 0 : acc) + w R; S <- Q + cdt R, or Q <- Q + dt acc
+};
+
+struct StageArgs {
+  int32_t mode;
+  int32_t first;  // RK4: first stage (acc not read); LSRK: a == 0
+  int32_t last;   // RK4: last stage (Q updated instead of S)
+  int32_t pad;
+  double a, b, dt;  // LSRK coefficients and step
+  double w, cdt;    // RK4 weight and next-stage offset c_{i+1} * dt
+};
+
+// Device buffers of one mesh (FP64 or FP32 operator path; the state is always FP64).
+struct DeviceMesh {
+  int p, n, Ns, Nfp;
+  int64_t E;
+  int prec;
+  int flux;
+  bool viscous;
+  double eta;
+  Physics phys;
+  Ops1D ops;
+  Ops1Df opsf;
+  // state registers [E][5][Ns] doubles
+  double *U = nullptr;   // solution (LSRK: U; RK4: Q)
+  double *R1 = nullptr;  // LSRK: dU; RK4: accumulator
+  double *R2 = nullptr;  // RK4: stage state S
+  // geometry
+  void *geo = nullptr;    // [E][10][Ns]: Ja[n][i] (9, n-major) then 1/|J|  (double or float)
+  void *fgeo = nullptr;   // [E][6][4][Nfp]: outward scaled normal N (3), BR2 factor sigma
+  FaceConn *conn = nullptr;  // [E][6]
+  void *face = nullptr;   // [E][6][20][Nfp]: U_f (5) then broken gradient G[i][v] (15, i-major)
+  int *flag = nullptr;    // non-finite flag
+  bool check_finite = false;
+  void *stream = nullptr;
+  int64_t bytes = 0;
+};
+
+// Host-side arrays of a mesh, built once by build_host_mesh (fr_host.cpp).
+struct HostMesh {
+  int p = 0, q = 1;
+  int64_t E = 0;
+  Ops1D ops;
+  std::vector<double> geo;     // [E][10][Ns]
+  std::vector<double> fgeo;    // [E][6][4][Nfp]
+  std::vector<FaceConn> conn;  // [E][6]
+  std::vector<double> xyz;     // [E][3][Ns]
+};
+
+// Returns "" on success or a message naming the offending element / face.
+std::string build_host_mesh(int p, int q, int64_t E, const int64_t *elem_vert, const double *elem_nodes,
+                            double br2_eta, HostMesh &H);
+
+}  // namespace frk

@@ -1,0 +1,853 @@
+// fr_kernels.hip -- gfx950 kernels of the FR residual and RK stage, and the C ABI of libfr.
+//
+// One RK stage is two kernels over elements (section "FR Algorithm", Eq. (3)):
+//
+//   K1 "pre-pass"  per element: the solution and the broken physical gradient
+//                  G = |J|^-1 sum_n Ja^n d_n U interpolated to the element's own face points,
+//                  written once to an element-major face buffer [E][6][20][Nfp].
+//   K3 "element"   per element: recomputes its own face values, reads the neighbours' from
+//                  the face buffer, forms the common state, the BR2 common gradient and the
+//                  common normal flux (Rusanov or Roe inviscid part minus the viscous part) at
+//                  every face point, then the corrected gradient, the pointwise flux, its
+//                  transformed divergence plus the g_DG flux correction, R = -div/|J|, and the
+//                  RK register update -- all without writing anything else to memory.
+//
+// Each face's common flux is computed by both elements that share it, from the same inputs in
+// the same order (the owner side acts as "left"), so the two values are bitwise opposite and
+// the scheme stays exactly conservative. The element's data move through LDS; threads map to
+// solution points for volume work and to face points for interface work.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fr.h"
+#include "fr_internal.h"
+
+using namespace frk;
+
+// ------------------------------------------------------------------------------------------
+// Device physics (Eq. (1)): inviscid flux, viscous flux with constant mu, Riemann solvers.
+// ------------------------------------------------------------------------------------------
+template <typename real>
+struct Phys {
+  real gamma, gm1, mu, kappa;
+};
+
+template <typename real>
+__device__ __forceinline__ real pressure(const real U[5], real gm1) {
+  const real ir = real(1) / U[0];
+  return gm1 * (U[4] - real(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir);
+}
+
+// Inviscid flux along a unit or scaled direction n: F(U).n, plus u.n and c.
+template <typename real>
+__device__ __forceinline__ void flux_n(const real U[5], const real n[3], const Phys<real> &ph, real F[5],
+                                       real &un, real &c) {
+  const real ir = real(1) / U[0];
+  const real u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
+  const real p = ph.gm1 * (U[4] - real(0.5) * U[0] * (u * u + v * v + w * w));
+  un = u * n[0] + v * n[1] + w * n[2];
+  F[0] = U[0] * un;
+  F[1] = U[1] * un + p * n[0];
+  F[2] = U[2] * un + p * n[1];
+  F[3] = U[3] * un + p * n[2];
+  F[4] = (U[4] + p) * un;
+  c = sqrt(ph.gamma * p * ir);
+}
+
+template <typename real>
+__device__ __forceinline__ void rusanov(const real UL[5], const real UR[5], const real n[3], const Phys<real> &ph,
+                                        real F[5]) {
+  real FL[5], FR[5], unL, unR, cL, cR;
+  flux_n(UL, n, ph, FL, unL, cL);
+  flux_n(UR, n, ph, FR, unR, cR);
+  const real lam = fmax(fabs(unL) + cL, fabs(unR) + cR);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lam * (UR[v] - UL[v]);
+}
+
+// Roe: mean flux minus half of sum |lambda_k| alpha_k r_k; sqrt(rho) averages; no entropy fix.
+template <typename real>
+__device__ __forceinline__ void roe(const real UL[5], const real UR[5], const real n[3], const Phys<real> &ph,
+                                    real F[5]) {
+  real FL[5], FR[5], t0, t1;
+  flux_n(UL, n, ph, FL, t0, t1);
+  flux_n(UR, n, ph, FR, t0, t1);
+  const real rL = UL[0], rR = UR[0];
+  const real iL = real(1) / rL, iR = real(1) / rR;
+  const real uL[3] = {UL[1] * iL, UL[2] * iL, UL[3] * iL};
+  const real uR[3] = {UR[1] * iR, UR[2] * iR, UR[3] * iR};
+  const real pL = ph.gm1 * (UL[4] - real(0.5) * rL * (uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]));
+  const real pR = ph.gm1 * (UR[4] - real(0.5) * rR * (uR[0] * uR[0] + uR[1] * uR[1] + uR[2] * uR[2]));
+  const real HL = (UL[4] + pL) * iL, HR = (UR[4] + pR) * iR;
+  const real sL = sqrt(rL), sR = sqrt(rR);
+  const real is = real(1) / (sL + sR);
+  const real rt = sL * sR;
+  real ut[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ut[i] = (sL * uL[i] + sR * uR[i]) * is;
+  const real Ht = (sL * HL + sR * HR) * is;
+  const real q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const real c2 = ph.gm1 * (Ht - real(0.5) * q2);
+  const real ct = sqrt(c2);
+  const real ic2 = real(1) / c2;
+  const real unt = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+  const real dr = rR - rL, dp = pR - pL;
+  const real du[3] = {uR[0] - uL[0], uR[1] - uL[1], uR[2] - uL[2]};
+  const real dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const real a1 = real(0.5) * (dp - rt * ct * dun) * ic2;
+  const real a5 = real(0.5) * (dp + rt * ct * dun) * ic2;
+  const real a2 = dr - dp * ic2;
+  const real l1 = fabs(unt - ct), l2 = fabs(unt), l5 = fabs(unt + ct);
+  const real w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2;
+  real dis[5];
+  dis[0] = w1 + w5 + w2;
+  real udu = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const real sh = du[i] - dun * n[i];
+    dis[1 + i] = w1 * (ut[i] - ct * n[i]) + w5 * (ut[i] + ct * n[i]) + w2 * ut[i] + l2 * rt * sh;
+    udu += ut[i] * sh;
+  }
+  dis[4] = w1 * (Ht - unt * ct) + w5 * (Ht + unt * ct) + w2 * real(0.5) * q2 + l2 * rt * udu;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * dis[v];
+}
+
+// Viscous flux Fv[i][v] from U and the gradient of the conserved variables G[i][v].
+template <typename real>
+__device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], const Phys<real> &ph, real Fv[3][5]) {
+  const real ir = real(1) / U[0];
+  const real u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
+  const real e = U[4] * ir;
+  real du[3][3], dT[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) du[i][j] = (G[i][1 + j] - u[j] * G[i][0]) * ir;
+    const real de = (G[i][4] - e * G[i][0]) * ir;
+    dT[i] = ph.gm1 * (de - (u[0] * du[i][0] + u[1] * du[i][1] + u[2] * du[i][2]));
+  }
+  const real lam = real(-2.0 / 3.0) * ph.mu * (du[0][0] + du[1][1] + du[2][2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    real tau[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tau[j] = ph.mu * (du[j][i] + du[i][j]) + (i == j ? lam : real(0));
+    Fv[i][0] = 0;
+    Fv[i][1] = tau[0];
+    Fv[i][2] = tau[1];
+    Fv[i][3] = tau[2];
+    Fv[i][4] = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + ph.kappa * dT[i];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Kernel configuration
+// ------------------------------------------------------------------------------------------
+template <int P>
+struct Cfg {
+  static constexpr int N = P + 1;
+  static constexpr int NS = N * N * N;
+  static constexpr int NFP = N * N;
+  static constexpr int NF = 6 * NFP;
+  static constexpr int EPB = (256 / NS) > 64 ? 64 : ((256 / NS) > 0 ? (256 / NS) : 1);  // elements per block
+  static constexpr int BLOCK = EPB * NS;
+};
+
+template <typename real>
+struct OpsT {
+  real D[kMaxN * kMaxN];
+  real lm[kMaxN];
+  real lp[kMaxN];
+  real gcL[kMaxN];
+  real gcR[kMaxN];
+};
+
+// index of solution point with coordinate c along direction d and (a, b) along the face's
+// tangential directions (increasing axis order)
+template <int N>
+__device__ __forceinline__ int line_pt(int d, int c, int a, int b) {
+  return d == 0 ? c + N * (a + N * b) : (d == 1 ? a + N * (c + N * b) : a + N * (b + N * c));
+}
+
+// ------------------------------------------------------------------------------------------
+// K1: element pre-pass
+// ------------------------------------------------------------------------------------------
+template <int P, typename real, bool VISC>
+__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass(const double *__restrict__ X,
+                                                           const real *__restrict__ geo,
+                                                           real *__restrict__ face, int64_t E,
+                                                           OpsT<real> ops) {
+  using C = Cfg<P>;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int NG = VISC ? 15 : 0;
+  __shared__ real sU[EPB][5][NS];
+  __shared__ real sG[EPB][NG > 0 ? NG : 1][NS];
+  const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const bool act = e < E;
+  const int i0 = t % N, i1 = (t / N) % N, i2 = t / (N * N);
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sU[slot][v][t] = real(X[(e * 5 + v) * NS + t]);
+  }
+  __syncthreads();
+  if (VISC && act) {
+    real ja[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
+    const real iJ = geo[(e * 10 + 9) * NS + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      real d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        d0 += ops.D[i0 * N + c] * sU[slot][v][c + N * (i1 + N * i2)];
+        d1 += ops.D[i1 * N + c] * sU[slot][v][i0 + N * (c + N * i2)];
+        d2 += ops.D[i2 * N + c] * sU[slot][v][i0 + N * (i1 + N * c)];
+      }
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        real g = ja[ii] * d0;
+        g += ja[3 + ii] * d1;
+        g += ja[6 + ii] * d2;
+        sG[slot][ii * 5 + v][t] = iJ * g;
+      }
+    }
+  }
+  __syncthreads();
+  if (!act) return;
+  for (int fp = t; fp < NF; fp += NS) {
+    const int f = fp / NFP, kk = fp - f * NFP;
+    const int a = kk % N, b = kk / N, d = f >> 1;
+    const real *ell = (f & 1) ? ops.lp : ops.lm;
+    real *dst = face + ((e * 6 + f) * 20) * NFP + kk;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      real acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += ell[c] * sU[slot][v][line_pt<N>(d, c, a, b)];
+      dst[v * NFP] = acc;
+    }
+    if (VISC) {
+#pragma unroll
+      for (int g = 0; g < 15; ++g) {
+        real acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][g][line_pt<N>(d, c, a, b)];
+        dst[(5 + g) * NFP] = acc;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// K3: fused element kernel (common fluxes, corrected gradient, divergence, RK update)
+// ------------------------------------------------------------------------------------------
+template <int P, typename real, bool VISC>
+__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_element(
+    const double *__restrict__ X, const real *__restrict__ geo, const real *__restrict__ fgeo,
+    const FaceConn *__restrict__ conn, const real *__restrict__ face, int64_t E, OpsT<real> ops,
+    Phys<real> ph, int flux, StageArgs st, double *__restrict__ out0, double *__restrict__ reg1,
+    double *__restrict__ reg2) {
+  using C = Cfg<P>;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int NG = VISC ? 15 : 0;
+  __shared__ real sU[EPB][5][NS];
+  __shared__ real sG[EPB][NG > 5 ? NG : 5][NS];  // broken gradient, later the transformed flux
+  constexpr int NJU = VISC ? NF : 1;
+  __shared__ real sJU[EPB][5][NJU];              // U^C - U_own at face points
+  __shared__ real sJF[EPB][5][NF];               // common flux along +xi_d, then its jump
+  const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const bool act = e < E;
+  const int idx[3] = {t % N, (t / N) % N, t / (N * N)};
+
+  real U[5];
+  real ja[9];
+  real iJ = 0;
+  real dU[3][5];
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      U[v] = real(X[(e * 5 + v) * NS + t]);
+      sU[slot][v][t] = U[v];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
+    iJ = geo[(e * 10 + 9) * NS + t];
+  }
+  __syncthreads();
+  // ---- phase A: reference gradient and broken physical gradient ----
+  if (VISC && act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      real d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        d0 += ops.D[idx[0] * N + c] * sU[slot][v][c + N * (idx[1] + N * idx[2])];
+        d1 += ops.D[idx[1] * N + c] * sU[slot][v][idx[0] + N * (c + N * idx[2])];
+        d2 += ops.D[idx[2] * N + c] * sU[slot][v][idx[0] + N * (idx[1] + N * c)];
+      }
+      dU[0][v] = d0;
+      dU[1][v] = d1;
+      dU[2][v] = d2;
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        real g = ja[ii] * d0;
+        g += ja[3 + ii] * d1;
+        g += ja[6 + ii] * d2;
+        sG[slot][ii * 5 + v][t] = iJ * g;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- phase B: common state and common normal flux at every face point ----
+  if (act) {
+    for (int fp = t; fp < NF; fp += NS) {
+      const int f = fp / NFP, kk = fp - f * NFP;
+      const int a = kk % N, b = kk / N, d = f >> 1;
+      const real *ell = (f & 1) ? ops.lp : ops.lm;
+      real uo[5], un[5];
+      real go[VISC ? 15 : 1], gn[VISC ? 15 : 1];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        real acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) acc += ell[c] * sU[slot][v][line_pt<N>(d, c, a, b)];
+        uo[v] = acc;
+      }
+      if (VISC) {
+#pragma unroll
+        for (int g = 0; g < 15; ++g) {
+          real acc = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][g][line_pt<N>(d, c, a, b)];
+          go[g] = acc;
+        }
+      }
+      const FaceConn cn = conn[e * 6 + f];
+      const int code = cn.code;
+      const int fn = code & 7;
+      const bool swp = (code >> 3) & 1, flu = (code >> 4) & 1, flv = (code >> 5) & 1, owner = (code >> 6) & 1;
+      const int uu = swp ? b : a, vv = swp ? a : b;
+      const int kn = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
+      const real *src = face + (((int64_t)cn.nbr * 6 + fn) * 20) * NFP + kn;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) un[v] = src[v * NFP];
+      if (VISC) {
+#pragma unroll
+        for (int g = 0; g < 15; ++g) gn[g] = src[(5 + g) * NFP];
+      }
+      const real *fg = fgeo + ((e * 6 + f) * 4) * NFP + kk;
+      real NL[3] = {fg[0], fg[NFP], fg[2 * NFP]};
+      if (!owner) {
+        NL[0] = -NL[0];
+        NL[1] = -NL[1];
+        NL[2] = -NL[2];
+      }
+      const real nm = sqrt(NL[0] * NL[0] + NL[1] * NL[1] + NL[2] * NL[2]);
+      const real inm = real(1) / nm;
+      const real nh[3] = {NL[0] * inm, NL[1] * inm, NL[2] * inm};
+      real UL[5], UR[5], UC[5], Fi[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        UL[v] = owner ? uo[v] : un[v];
+        UR[v] = owner ? un[v] : uo[v];
+        UC[v] = real(0.5) * (UL[v] + UR[v]);
+      }
+      if (flux == 0) rusanov(UL, UR, nh, ph, Fi);
+      else roe(UL, UR, nh, ph, Fi);
+      if (VISC) {
+        const real sig = fg[3 * NFP];
+        real GI[3][5];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+            GI[i][v] = real(0.5) * (go[i * 5 + v] + gn[i * 5 + v]) + sig * NL[i] * (UR[v] - UL[v]);
+        real Fv[3][5];
+        visc_flux(UC, GI, ph, Fv);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fi[v] -= Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
+      }
+      // owner: F^{I,perp}_own = nm Fi; other side: -nm Fi. Stored along +xi_d: times s.
+      const real sg = ((f & 1) ? real(1) : real(-1)) * (owner ? real(1) : real(-1));
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        sJF[slot][v][fp] = sg * (nm * Fi[v]);
+        if (VISC) sJU[slot][v][fp % NJU] = UC[v] - uo[v];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- phase C: corrected gradient and pointwise flux ----
+  real F[3][5];
+  if (act) {
+    if (VISC) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
+        const int kk = idx[u] + N * idx[w];
+        const real cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          dU[d][v] += sJU[slot][v][((2 * d) * NFP + kk) % NJU] * cL + sJU[slot][v][((2 * d + 1) * NFP + kk) % NJU] * cR;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const real ei[3] = {real(i == 0), real(i == 1), real(i == 2)};
+      real un_, c_;
+      flux_n(U, ei, ph, F[i], un_, c_);
+    }
+    if (VISC) {
+      real G[3][5];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          real g = ja[i] * dU[0][v];
+          g += ja[3 + i] * dU[1][v];
+          g += ja[6 + i] * dU[2][v];
+          G[i][v] = iJ * g;
+        }
+      real Fv[3][5];
+      visc_flux(U, G, ph, Fv);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[i][v] -= Fv[i][v];
+    }
+  }
+  // ---- phase D: divergence of the transformed flux and the flux correction, per direction ----
+  real div[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();  // previous users of sG / sJF are done
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sG[slot][v][t] = ja[d * 3 + 0] * F[0][v] + ja[d * 3 + 1] * F[1][v] + ja[d * 3 + 2] * F[2][v];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        real acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          int id2[3] = {idx[0], idx[1], idx[2]};
+          id2[d] = c;
+          acc += ops.D[idx[d] * N + c] * sG[slot][v][id2[0] + N * (id2[1] + N * id2[2])];
+        }
+        div[v] += acc;
+      }
+      for (int fp = t; fp < 2 * NFP; fp += NS) {
+        const int f = 2 * d + fp / NFP, kk = fp % NFP;
+        const int a = kk % N, b = kk / N;
+        const real *ell = (f & 1) ? ops.lp : ops.lm;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          real acc = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][v][line_pt<N>(d, c, a, b)];
+          sJF[slot][v][f * NFP + kk] -= acc;
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
+      const int kk = idx[u] + N * idx[w];
+      const real cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        div[v] += sJF[slot][v][(2 * d) * NFP + kk] * cL + sJF[slot][v][(2 * d + 1) * NFP + kk] * cR;
+    }
+  }
+  if (!act) return;
+  // ---- R = -div / |J| and the RK register update ----
+  const int64_t base = e * 5 * NS + t;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double R = -double(div[v]) * double(iJ);
+    const int64_t o = base + v * NS;
+    if (st.mode == kModeResidual) {
+      out0[o] = R;
+    } else if (st.mode == kModeLSRK) {
+      // out0 = U (read and written), reg1 = dU
+      const double du = (st.first ? 0.0 : st.a * reg1[o]) + st.dt * R;
+      reg1[o] = du;
+      out0[o] = out0[o] + st.b * du;
+    } else {
+      // RK4: out0 = Q, reg1 = accumulator, reg2 = stage state S
+      const double acc = (st.first ? 0.0 : reg1[o]) + st.w * R;
+      if (!st.last) {
+        reg1[o] = acc;
+        reg2[o] = out0[o] + st.cdt * R;
+      } else {
+        out0[o] = out0[o] + st.dt * acc;
+      }
+    }
+  }
+}
+
+__global__ void k_nonfinite(const double *__restrict__ R, int64_t n, int *flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (; i < n; i += stride) bad |= !isfinite(R[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+// ==========================================================================================
+// Host side: handle, dispatch, C ABI
+// ==========================================================================================
+struct fr_mesh_s {
+  uint64_t magic;
+  DeviceMesh dm;
+  std::vector<double> xyz;
+  int device;
+};
+
+static constexpr uint64_t kMagic = 0x46524d4553484d31ull;  // "FRMESHM1"
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(FR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static bool valid(fr_mesh_t m) { return m != nullptr && m->magic == kMagic; }
+
+template <int P, typename real, bool VISC>
+static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
+                          float *k1_ms, float *k3_ms) {
+  using C = Cfg<P>;
+  OpsT<real> ops;
+  for (int i = 0; i < kMaxN * kMaxN; ++i) ops.D[i] = real(dm.ops.D[i]);
+  for (int i = 0; i < kMaxN; ++i) {
+    ops.lm[i] = real(dm.ops.lm[i]);
+    ops.lp[i] = real(dm.ops.lp[i]);
+    ops.gcL[i] = real(dm.ops.gcL[i]);
+    ops.gcR[i] = real(dm.ops.gcR[i]);
+  }
+  Phys<real> ph{real(dm.phys.gamma), real(dm.phys.gamma - 1.0), real(dm.phys.mu), real(dm.phys.kappa)};
+  const int64_t blocks = (dm.E + C::EPB - 1) / C::EPB;
+  hipStream_t s = (hipStream_t)dm.stream;
+  hipEvent_t ev[3];
+  const bool timed = k1_ms != nullptr;
+  if (timed) {
+    for (int i = 0; i < 3; ++i) HIPCHK(hipEventCreate(&ev[i]));
+    HIPCHK(hipEventRecord(ev[0], s));
+  }
+  hipLaunchKernelGGL((k_prepass<P, real, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+                     (const real *)dm.geo, (real *)dm.face, dm.E, ops);
+  HIPCHK(hipGetLastError());
+  if (timed) HIPCHK(hipEventRecord(ev[1], s));
+  hipLaunchKernelGGL((k_element<P, real, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+                     (const real *)dm.geo, (const real *)dm.fgeo, dm.conn, (const real *)dm.face, dm.E, ops, ph,
+                     dm.flux, st, out0, reg1, reg2);
+  HIPCHK(hipGetLastError());
+  if (timed) {
+    HIPCHK(hipEventRecord(ev[2], s));
+    HIPCHK(hipEventSynchronize(ev[2]));
+    HIPCHK(hipEventElapsedTime(k1_ms, ev[0], ev[1]));
+    HIPCHK(hipEventElapsedTime(k3_ms, ev[1], ev[2]));
+    for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+  }
+  return FR_OK;
+}
+
+template <typename real, bool VISC>
+static int launch_stage_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
+                          float *t1, float *t3) {
+  switch (dm.p) {
+    case 0: return launch_stage_t<0, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 1: return launch_stage_t<1, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 2: return launch_stage_t<2, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 3: return launch_stage_t<3, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 4: return launch_stage_t<4, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 5: return launch_stage_t<5, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 6: return launch_stage_t<6, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 7: return launch_stage_t<7, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    default: return fail(FR_ERR_UNSUPPORTED, "p out of range");
+  }
+}
+
+static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
+                        float *t1 = nullptr, float *t3 = nullptr) {
+  if (dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "only FR_FP64 is built in this path");
+  return dm.viscous ? launch_stage_p<double, true>(dm, X, st, o, r1, r2, t1, t3)
+                    : launch_stage_p<double, false>(dm, X, st, o, r1, r2, t1, t3);
+}
+
+// Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients.
+static const double kLsA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double kLsB[5] = {1432997174477.0 / 9575080441237.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms_acc) {
+  DeviceMesh &dm = m->dm;
+  const int64_t M = dm.E * 5 * dm.Ns;
+  float t1 = 0, t3 = 0;
+  float *p1 = ms_acc ? &t1 : nullptr, *p3 = ms_acc ? &t3 : nullptr;
+  for (int step = 0; step < n_steps; ++step) {
+    if (scheme == FR_LSRK45) {
+      if (!dm.R1) {
+        HIPCHK(hipMalloc(&dm.R1, M * sizeof(double)));
+        dm.bytes += M * sizeof(double);
+      }
+      for (int s = 0; s < 5; ++s) {
+        StageArgs st{};
+        st.mode = kModeLSRK;
+        st.first = s == 0;
+        st.a = kLsA[s];
+        st.b = kLsB[s];
+        st.dt = dt;
+        int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, p1, p3);
+        if (rc) return rc;
+        if (ms_acc) { ms_acc[0] += t1; ms_acc[1] += t3; ms_acc[2] += 1; }
+      }
+    } else if (scheme == FR_RK4) {
+      if (!dm.R1) {
+        HIPCHK(hipMalloc(&dm.R1, M * sizeof(double)));
+        dm.bytes += M * sizeof(double);
+      }
+      if (!dm.R2) {
+        HIPCHK(hipMalloc(&dm.R2, M * sizeof(double)));
+        dm.bytes += M * sizeof(double);
+      }
+      const double w[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+      const double c[4] = {0.5, 0.5, 1.0, 0.0};
+      for (int s = 0; s < 4; ++s) {
+        StageArgs st{};
+        st.mode = kModeRK4;
+        st.first = s == 0;
+        st.last = s == 3;
+        st.w = w[s];
+        st.cdt = c[s] * dt;
+        st.dt = dt;
+        const double *X = s == 0 ? dm.U : dm.R2;
+        int rc = launch_stage(dm, X, st, dm.U, dm.R1, dm.R2, p1, p3);
+        if (rc) return rc;
+        if (ms_acc) { ms_acc[0] += t1; ms_acc[1] += t3; ms_acc[2] += 1; }
+      }
+    } else {
+      return fail(FR_ERR_ARG, "unknown scheme");
+    }
+  }
+  return FR_OK;
+}
+
+extern "C" {
+
+const char *fr_last_error(void) { return g_err.c_str(); }
+
+int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
+  if (!out) return fail(FR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(FR_ERR_ARG, "desc is NULL");
+  if (d->p < 0 || d->p > kMaxP) return fail(FR_ERR_ARG, "p must be in 0..7");
+  if (d->q < 1 || d->q > (d->p > 1 ? d->p : 1)) return fail(FR_ERR_ARG, "q must be in 1..max(p,1)");
+  if (d->n_elem <= 0 || d->n_elem > (int64_t)INT32_MAX) return fail(FR_ERR_ARG, "n_elem out of range");
+  if (!d->elem_vert || !d->elem_nodes) return fail(FR_ERR_ARG, "elem_vert / elem_nodes is NULL");
+  if (d->flux != FR_RUSANOV && d->flux != FR_ROE) return fail(FR_ERR_ARG, "unknown flux");
+  if (d->prec != FR_FP64 && d->prec != FR_FP32) return fail(FR_ERR_ARG, "unknown precision");
+  if (d->prec == FR_FP32) return fail(FR_ERR_UNSUPPORTED, "FR_FP32 is not built yet");
+  if (!(d->gamma > 1.0) || !(d->prandtl > 0.0) || !(d->mu >= 0.0) || !(d->br2_eta >= 0.0))
+    return fail(FR_ERR_ARG, "gamma > 1, prandtl > 0, mu >= 0 and br2_eta >= 0 are required");
+  if (d->reserved != 0) return fail(FR_ERR_ARG, "reserved must be 0");
+
+  HostMesh H;
+  std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->br2_eta, H);
+  if (!err.empty()) return fail(FR_ERR_MESH, err);
+
+  fr_mesh_s *m = new fr_mesh_s();
+  m->magic = kMagic;
+  DeviceMesh &dm = m->dm;
+  dm.p = d->p;
+  dm.n = d->p + 1;
+  dm.Ns = dm.n * dm.n * dm.n;
+  dm.Nfp = dm.n * dm.n;
+  dm.E = d->n_elem;
+  dm.prec = d->prec;
+  dm.flux = d->flux;
+  dm.viscous = d->mu > 0.0;
+  dm.eta = d->br2_eta;
+  dm.phys = Physics{d->gamma, d->prandtl, d->mu, d->mu * d->gamma / (d->prandtl * (d->gamma - 1.0))};
+  dm.ops = H.ops;
+  dm.stream = hip_stream;
+  m->xyz = std::move(H.xyz);
+  (void)hipGetDevice(&m->device);
+
+  auto alloc = [&](void **p, size_t bytes) -> int {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? FR_ERR_OOM : FR_ERR_HIP,
+                                     std::string("hipMalloc: ") + hipGetErrorString(e));
+    dm.bytes += bytes;
+    return FR_OK;
+  };
+  const size_t M = (size_t)dm.E * 5 * dm.Ns;
+  int rc = FR_OK;
+  if (!rc) rc = alloc((void **)&dm.U, M * sizeof(double));
+  if (!rc) rc = alloc(&dm.geo, H.geo.size() * sizeof(double));
+  if (!rc) rc = alloc(&dm.fgeo, H.fgeo.size() * sizeof(double));
+  if (!rc) rc = alloc((void **)&dm.conn, H.conn.size() * sizeof(FaceConn));
+  if (!rc) rc = alloc(&dm.face, (size_t)dm.E * 6 * 20 * dm.Nfp * sizeof(double));
+  if (!rc) rc = alloc((void **)&dm.flag, sizeof(int));
+  if (rc) {
+    fr_mesh_destroy(m);
+    return rc;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e1 = hipMemcpyAsync(dm.geo, H.geo.data(), H.geo.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  hipError_t e2 = hipMemcpyAsync(dm.fgeo, H.fgeo.data(), H.fgeo.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  hipError_t e3 = hipMemcpyAsync(dm.conn, H.conn.data(), H.conn.size() * sizeof(FaceConn), hipMemcpyHostToDevice, s);
+  hipError_t e4 = hipMemsetAsync(dm.U, 0, M * sizeof(double), s);
+  hipError_t e5 = hipStreamSynchronize(s);  // host vectors die at return
+  if (e1 || e2 || e3 || e4 || e5) {
+    fr_mesh_destroy(m);
+    return fail(FR_ERR_HIP, "upload of mesh data failed");
+  }
+  dm.check_finite = d->check_finite != 0;
+  *out = m;
+  return FR_OK;
+}
+
+int fr_mesh_geometry_host(const fr_mesh_desc *d, double *geo, double *fgeo, int32_t *conn, double *xyz) {
+  if (!d || !d->elem_vert || !d->elem_nodes) return fail(FR_ERR_ARG, "NULL descriptor or arrays");
+  if (d->p < 0 || d->p > kMaxP) return fail(FR_ERR_ARG, "p must be in 0..7");
+  if (d->q < 1 || d->q > (d->p > 1 ? d->p : 1)) return fail(FR_ERR_ARG, "q must be in 1..max(p,1)");
+  if (d->n_elem <= 0 || d->n_elem > (int64_t)INT32_MAX) return fail(FR_ERR_ARG, "n_elem out of range");
+  HostMesh H;
+  std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->br2_eta, H);
+  if (!err.empty()) return fail(FR_ERR_MESH, err);
+  if (geo) std::memcpy(geo, H.geo.data(), H.geo.size() * sizeof(double));
+  if (fgeo) std::memcpy(fgeo, H.fgeo.data(), H.fgeo.size() * sizeof(double));
+  if (conn) std::memcpy(conn, H.conn.data(), H.conn.size() * sizeof(FaceConn));
+  if (xyz) std::memcpy(xyz, H.xyz.data(), H.xyz.size() * sizeof(double));
+  return FR_OK;
+}
+
+int fr_mesh_destroy(fr_mesh_t m) {
+  if (!m) return FR_OK;
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  DeviceMesh &dm = m->dm;
+  if (dm.stream) (void)hipStreamSynchronize((hipStream_t)dm.stream);
+  else (void)hipDeviceSynchronize();
+  void *bufs[] = {dm.U, dm.R1, dm.R2, dm.geo, dm.fgeo, dm.conn, dm.face, dm.flag};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  m->magic = 0;
+  delete m;
+  return FR_OK;
+}
+
+int fr_set_stream(fr_mesh_t m, void *hip_stream) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  m->dm.stream = hip_stream;
+  return FR_OK;
+}
+
+int fr_sol_coords(fr_mesh_t m, double *xyz) {
+  if (!valid(m) || !xyz) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  std::memcpy(xyz, m->xyz.data(), m->xyz.size() * sizeof(double));
+  return FR_OK;
+}
+
+int fr_set_state(fr_mesh_t m, const double *U, int on_device) {
+  if (!valid(m) || !U) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  DeviceMesh &dm = m->dm;
+  const size_t bytes = (size_t)dm.E * 5 * dm.Ns * sizeof(double);
+  hipStream_t s = (hipStream_t)dm.stream;
+  HIPCHK(hipMemcpyAsync(dm.U, U, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));
+  return FR_OK;
+}
+
+int fr_get_state(fr_mesh_t m, double *U, int on_device) {
+  if (!valid(m) || !U) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  DeviceMesh &dm = m->dm;
+  const size_t bytes = (size_t)dm.E * 5 * dm.Ns * sizeof(double);
+  hipStream_t s = (hipStream_t)dm.stream;
+  HIPCHK(hipMemcpyAsync(U, dm.U, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));
+  return FR_OK;
+}
+
+int fr_residual(fr_mesh_t m, double *R, int on_device) {
+  if (!valid(m) || !R) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  DeviceMesh &dm = m->dm;
+  const size_t M = (size_t)dm.E * 5 * dm.Ns;
+  hipStream_t s = (hipStream_t)dm.stream;
+  double *dst = R;
+  double *tmp = nullptr;
+  if (!on_device) {
+    HIPCHK(hipMalloc(&tmp, M * sizeof(double)));
+    dst = tmp;
+  }
+  StageArgs st{};
+  st.mode = kModeResidual;
+  int rc = launch_stage(dm, dm.U, st, dst, nullptr, nullptr);
+  if (rc == FR_OK && dm.check_finite) {
+    int bad = 0;
+    hipError_t e = hipMemsetAsync(dm.flag, 0, sizeof(int), s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_nonfinite, dim3(1024), dim3(256), 0, s, dst, (int64_t)M, dm.flag);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, dm.flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(FR_ERR_HIP, std::string("non-finite scan: ") + hipGetErrorString(e));
+    else if (bad) rc = fail(FR_ERR_NONFINITE, "the residual holds a NaN or Inf");
+  }
+  if (rc == FR_OK && !on_device) {
+    hipError_t e = hipMemcpyAsync(R, tmp, M * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(FR_ERR_HIP, std::string("copy back: ") + hipGetErrorString(e));
+  }
+  if (tmp) (void)hipFree(tmp);
+  return rc;
+}
+
+int fr_rk_step(fr_mesh_t m, double dt, int scheme, int n_steps) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (n_steps < 0 || !std::isfinite(dt)) return fail(FR_ERR_ARG, "bad dt or n_steps");
+  return run_steps(m, dt, scheme, n_steps, nullptr);
+}
+
+int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_bytes) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (n_elem) *n_elem = m->dm.E;
+  if (n_sol) *n_sol = m->dm.Ns;
+  if (device_bytes) *device_bytes = m->dm.bytes;
+  return FR_OK;
+}
+
+int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms) {
+  if (!valid(m) || !ms) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  double acc[3] = {0, 0, 0};
+  int rc = run_steps(m, dt, scheme, n_steps, acc);
+  if (rc) return rc;
+  ms[0] = acc[2] > 0 ? acc[0] / acc[2] : 0;
+  ms[1] = acc[2] > 0 ? acc[1] / acc[2] : 0;
+  return FR_OK;
+}
+
+}  // extern "C"

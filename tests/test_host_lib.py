@@ -1,0 +1,74 @@
+"""CPU-side checks of libfr: it loads, exports every symbol include/fr.h declares, and its host
+mesh setup (face pairing, orientation, curl-form metrics, normals) agrees with the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_06605_amd import fr
+from paper_2308_06605_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fr.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(fr_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fr.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("n,p,q,scramble", [(3, 3, 3, False), (3, 3, 3, True), (4, 2, 1, True),
+                                            (3, 7, 7, True), (3, 0, 1, True), (3, 5, 3, True)])
+def test_host_setup_matches_oracle(n, p, q, scramble):
+    m = I.box_mesh(n, q=q, curve_amp=0.05 if p > 0 else 0.0, curve_mode="mixed")
+    if scramble:
+        m, _ = I.scramble_mesh(m, seed=3)
+    geo, fgeo, conn, xyz = fr.geometry_host(m, p)
+    o = oracle.Oracle(m, p)
+    Ja, dJ, Nf, _ = o.geometry()
+    nbr, nface, owner, perm = o.connectivity()
+    E, Ns = geo.shape[0], geo.shape[2]
+    ja_lib = np.transpose(geo[:, :9, :], (0, 2, 1)).reshape(E, Ns, 3, 3)
+    scale = max(1.0, np.abs(Ja).max())
+    assert np.abs(ja_lib - Ja).max() < 4e-15 * scale
+    assert np.abs(geo[:, 9, :] * dJ - 1).max() < 1e-14
+    assert np.abs(xyz - o.sol_coords()).max() < 1e-14
+    assert np.array_equal(conn[:, :, 0], nbr)
+    assert np.array_equal(conn[:, :, 1] & 7, nface)
+    assert np.array_equal((conn[:, :, 1] >> 6) & 1, owner)
+    assert np.abs(np.transpose(fgeo[:, :, :3, :], (0, 1, 3, 2)) - Nf).max() < 4e-15 * scale
+    N1 = p + 1
+    code = conn[:, :, 1]
+    for e in range(E):
+        for f in range(6):
+            swp, fu, fv = (code[e, f] >> 3) & 1, (code[e, f] >> 4) & 1, (code[e, f] >> 5) & 1
+            for b in range(N1):
+                for a in range(N1):
+                    uu, vv = (b, a) if swp else (a, b)
+                    kn = (p - uu if fu else uu) + N1 * (p - vv if fv else vv)
+                    assert kn == perm[e, f, a + N1 * b]
+
+
+def test_host_setup_errors():
+    m = I.box_mesh(3, q=1)
+    bad = I.Mesh(elem_vert=m.elem_vert[:-1].copy(), elem_nodes=m.elem_nodes[:-1].copy(), q=1)
+    with pytest.raises(fr.FRError) as ei:
+        fr.geometry_host(bad, 2)
+    assert ei.value.name == "FR_ERR_MESH" and "unpaired" in str(ei.value)
+    inv = I.Mesh(elem_vert=m.elem_vert.copy(), elem_nodes=m.elem_nodes.copy(), q=1)
+    inv.elem_nodes[4, :, 0] *= -1.0
+    with pytest.raises(fr.FRError) as ei:
+        fr.geometry_host(inv, 2)
+    assert ei.value.name == "FR_ERR_MESH" and "Jacobian" in str(ei.value)
+    with pytest.raises(fr.FRError) as ei:
+        fr.geometry_host(m, 9)
+    assert ei.value.name == "FR_ERR_ARG"
