@@ -106,26 +106,36 @@ int fr_get_state(fr_mesh_t m, double *U, int on_device);
 int fr_residual(fr_mesh_t m, double *R, int on_device);
 
 /* Advance the state by n_steps explicit Runge-Kutta steps of size dt (enum fr_scheme). Every
- * stage is two kernels: the element pre-pass (solution and broken gradient to the faces) and
- * the fused element pass (common fluxes, corrected gradient, flux divergence and correction,
- * and the RK register update). Enqueued on the stream; returns without waiting. */
+ * stage is three kernels: the element pre-pass (solution and broken gradient to the faces),
+ * the face kernel (common state, BR2 common gradient and common normal flux, once per face
+ * point) and the volume kernel (corrected gradient, flux divergence and correction, and the
+ * RK register update). Enqueued on the stream; returns without waiting. */
 int fr_rk_step(fr_mesh_t m, double dt, int scheme, int n_steps);
 
 /* Sizes of the handle: n_elem, points per element, bytes of device memory held. */
 int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_bytes);
 
 /* Measurement helper: run n_steps RK steps with each kernel launch bracketed by HIP events on
- * the handle's stream, and return the mean duration in milliseconds of the pre-pass kernel
- * (ms[0]) and of the fused element kernel (ms[1]) over all stages. Waits for the stream. */
+ * the handle's stream, and return the mean duration in milliseconds per stage of the element
+ * pre-pass (ms[0]), the face kernel (ms[1]) and the volume kernel with the RK update (ms[2]).
+ * Waits for the stream. */
 int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms);
 
 /* Host-only: run the mesh setup of fr_mesh_create without a GPU and return its arrays, for
- * inspection. geo [n_elem][10][N_s]: rows |J| dxi_n/dx_i (n-major, 9) then 1/|J|;
- * fgeo [n_elem][6][4][N_fp]: the face's scaled normal as seen from this side (3) and the BR2
- * factor sigma; conn [n_elem][6][2]: neighbour element and packed code (bits 0-2 neighbour
- * face, 3 swap, 4 flip u, 5 flip v, 6 this side owns the face); xyz [n_elem][3][N_s].
- * Any output pointer may be NULL. Errors: FR_ERR_ARG, FR_ERR_MESH. */
-int fr_mesh_geometry_host(const fr_mesh_desc *desc, double *geo, double *fgeo, int32_t *conn, double *xyz);
+ * inspection. Faces are numbered in owner order (the owner of a face is the side with the
+ * smaller element index, then the smaller local face); a fully paired mesh has 3 n_elem.
+ *   geo  [n_elem][10][N_s]: rows |J| dxi_n/dx_i (n-major, 9) then 1/|J|;
+ *   fgeo [3 n_elem][4][N_fp]: the owner's outward scaled normal (3) and the BR2 factor
+ *        sigma = eta (p+1)^2/8 (1/|J|_L + 1/|J|_R) at each owner face point;
+ *   ftab [3 n_elem][4]: owner element, other element, code (bits 0-2 owner's face, 3-5 other
+ *        face, 6 swap, 7 flip u, 8 flip v: the owner point -> other point map), 0;
+ *   conn [n_elem][6][2]: neighbour element and packed code (bits 0-2 neighbour face, 3 swap,
+ *        4 flip u, 5 flip v, 6 this side owns the face);
+ *   xyz  [n_elem][3][N_s] solution-point coordinates.
+ * Point (a, b) maps to (u', v') with (u, v) = swap ? (b, a) : (a, b), u' = flip_u ? p-u : u,
+ * v' = flip_v ? p-v : v. Any output pointer may be NULL. Errors: FR_ERR_ARG, FR_ERR_MESH. */
+int fr_mesh_geometry_host(const fr_mesh_desc *desc, double *geo, double *fgeo, int32_t *ftab, int32_t *conn,
+                          double *xyz);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *fr_last_error(void);

@@ -543,35 +543,43 @@ std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const do
       // 1/|J| from the rounded |J|, as a double division
       H.geo[((size_t)e * 10 + 9) * Ns + s] = 1.0 / (double)G.detj[(size_t)e * Ns + s];
     }
-  // face geometry: the owner's outward normal on both sides (negated for the other side) and
-  // the BR2 factor sigma = eta (p+1)^2/2 (1/|J|_L + 1/|J|_R) / 4
-  H.fgeo.assign((size_t)E * 6 * 4 * Nfp, 0);
+  // faces in owner order: the owner's outward normal and the BR2 factor
+  // sigma = eta (p+1)^2/2 (1/|J|_L + 1/|J|_R) / 4 per face point
   H.conn = T.conn;
+  H.ftab.clear();
+  H.fref.assign((size_t)E * 6, FaceRef{-1, 0});
   const LD cl = (LD)(n * n) / 2;
   for (int64_t e = 0; e < E; ++e)
     for (int f = 0; f < 6; ++f) {
       const FaceConn c = T.conn[e * 6 + f];
-      const bool owner = (c.code >> 6) & 1;
-      const int64_t en = c.nbr;
+      if (!((c.code >> 6) & 1)) continue;
+      const int32_t fid = (int32_t)H.ftab.size();
       const int fn = c.code & 7;
-      for (int k = 0; k < Nfp; ++k) {
-        const int kn = T.perm[(e * 6 + f) * Nfp + k];
-        double N[3];
-        for (int i = 0; i < 3; ++i) {
-          LD nl = owner ? G.nface[(((size_t)e * 6 + f) * Nfp + k) * 3 + i]
-                        : G.nface[(((size_t)en * 6 + fn) * Nfp + kn) * 3 + i];
-          N[i] = owner ? (double)nl : -(double)nl;
-        }
-        double jo = (double)G.jface[((size_t)e * 6 + f) * Nfp + k];
-        double jn = (double)G.jface[((size_t)en * 6 + fn) * Nfp + kn];
-        LD sig = (LD)eta * cl * (1.0L / (LD)jo + 1.0L / (LD)jn) / 4;
-        double *dst = &H.fgeo[((size_t)e * 6 + f) * 4 * Nfp];
-        dst[0 * Nfp + k] = N[0];
-        dst[1 * Nfp + k] = N[1];
-        dst[2 * Nfp + k] = N[2];
-        dst[3 * Nfp + k] = (double)sig;
-      }
+      FaceRec r;
+      r.eL = (int32_t)e;
+      r.eR = c.nbr;
+      r.code = f | (fn << 3) | (((c.code >> 3) & 7) << 6);
+      r.pad = 0;
+      H.ftab.push_back(r);
+      H.fref[e * 6 + f] = FaceRef{fid, 64};
+      // the other side maps its points to the owner's with its own FaceConn bits
+      const FaceConn co = T.conn[(size_t)c.nbr * 6 + fn];
+      H.fref[(size_t)c.nbr * 6 + fn] = FaceRef{fid, co.code & (8 | 16 | 32)};
     }
+  const int64_t F = (int64_t)H.ftab.size();
+  H.fgeo.assign((size_t)F * 4 * Nfp, 0);
+  for (int64_t fid = 0; fid < F; ++fid) {
+    const FaceRec &r = H.ftab[fid];
+    const int fL = r.code & 7, fR = (r.code >> 3) & 7;
+    double *dst = &H.fgeo[(size_t)fid * 4 * Nfp];
+    for (int k = 0; k < Nfp; ++k) {
+      const int kr = T.perm[((size_t)r.eL * 6 + fL) * Nfp + k];
+      for (int i = 0; i < 3; ++i) dst[i * Nfp + k] = (double)G.nface[(((size_t)r.eL * 6 + fL) * Nfp + k) * 3 + i];
+      const double jl = (double)G.jface[((size_t)r.eL * 6 + fL) * Nfp + k];
+      const double jr = (double)G.jface[((size_t)r.eR * 6 + fR) * Nfp + kr];
+      dst[3 * Nfp + k] = (double)((LD)eta * cl * (1.0L / (LD)jl + 1.0L / (LD)jr) / 4);
+    }
+  }
   return "";
 }
 

@@ -41,6 +41,13 @@ struct FaceConn {
   int32_t code;
 };
 
+// Per element face, for the volume kernel: the face record index and the map from this
+// side's face point to the owner's (the same bits as FaceConn.code; identity for the owner).
+struct FaceRef {
+  int32_t fid;
+  int32_t code;
+};
+
 struct Physics {
   double gamma;
   double prandtl;
@@ -48,7 +55,17 @@ struct Physics {
   double kappa;  // mu * gamma / (prandtl * (gamma - 1)): heat-flux coefficient on d(p/rho)
 };
 
-// RK stage parameters for the fused element kernel.
+// One face (owner side "L", other side "R"), the unit of the face kernel.
+//   eL, eR : elements; code: bits 0-2 L's local face, 3-5 R's local face, 6 swap, 7 flip u,
+//   8 flip v -- the map from L's face point (a, b) to R's point, as in FaceConn.
+struct FaceRec {
+  int32_t eL;
+  int32_t eR;
+  int32_t code;
+  int32_t pad;
+};
+
+// RK stage parameters for the volume kernel.
 enum StageMode : int32_t {
   kModeResidual = 0,  // write R
   kModeLSRK = 1,      // dU <- a dU + dt R; U <- U + b dU   (a == 0: dU is not read)
@@ -81,9 +98,12 @@ struct DeviceMesh {
   double *R2 = nullptr;  // RK4: stage state S
   // geometry
   void *geo = nullptr;    // [E][10][Ns]: Ja[n][i] (9, n-major) then 1/|J|  (double or float)
-  void *fgeo = nullptr;   // [E][6][4][Nfp]: outward scaled normal N (3), BR2 factor sigma
-  FaceConn *conn = nullptr;  // [E][6]
+  int64_t F = 0;          // number of faces
+  void *fgeo = nullptr;   // [F][4][Nfp]: owner's outward scaled normal N (3), BR2 factor sigma
+  FaceRec *ftab = nullptr;   // [F]
+  FaceRef *fref = nullptr;   // [E][6]
   void *face = nullptr;   // [E][6][20][Nfp]: U_f (5) then broken gradient G[i][v] (15, i-major)
+  void *fout = nullptr;   // [F][10][Nfp]: J = (U_R - U_L)/2 (5), owner's F^{I,perp} (5)
   int *flag = nullptr;    // non-finite flag
   bool check_finite = false;
   void *stream = nullptr;
@@ -96,8 +116,10 @@ struct HostMesh {
   int64_t E = 0;
   Ops1D ops;
   std::vector<double> geo;     // [E][10][Ns]
-  std::vector<double> fgeo;    // [E][6][4][Nfp]
+  std::vector<double> fgeo;    // [F][4][Nfp]
   std::vector<FaceConn> conn;  // [E][6]
+  std::vector<FaceRec> ftab;   // [F]
+  std::vector<FaceRef> fref;   // [E][6]
   std::vector<double> xyz;     // [E][3][Ns]
 };
 

@@ -249,159 +249,123 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass(const double *__restr
 }
 
 // ------------------------------------------------------------------------------------------
-// K3: fused element kernel (common fluxes, corrected gradient, divergence, RK update)
+// K2: face kernel. One thread per face point of each face (owner side L): the common state,
+// the BR2 common gradient and the common normal flux, computed once per face point.
+// Writes J = (U_R - U_L)/2 = U^C - U_L and the owner's transformed common normal flux
+// F^{I,perp}_L = |N| (F*_inv - F_v(U^C, G^I) . n) to a face-major buffer [F][10][Nfp].
 // ------------------------------------------------------------------------------------------
 template <int P, typename real, bool VISC>
-__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_element(
-    const double *__restrict__ X, const real *__restrict__ geo, const real *__restrict__ fgeo,
-    const FaceConn *__restrict__ conn, const real *__restrict__ face, int64_t E, OpsT<real> ops,
-    Phys<real> ph, int flux, StageArgs st, double *__restrict__ out0, double *__restrict__ reg1,
-    double *__restrict__ reg2) {
+__global__ __launch_bounds__(256) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
+                                              const FaceRec *__restrict__ ftab, int64_t F, Phys<real> ph,
+                                              int flux, real *__restrict__ fout) {
+  constexpr int N = P + 1, NFP = N * N;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t fc = gid / NFP;
+  if (fc >= F) return;
+  const int kk = (int)(gid - fc * NFP);
+  const FaceRec r = ftab[fc];
+  const int fL = r.code & 7, fR = (r.code >> 3) & 7;
+  const bool swp = (r.code >> 6) & 1, flu = (r.code >> 7) & 1, flv = (r.code >> 8) & 1;
+  const int a = kk % N, b = kk / N;
+  const int uu = swp ? b : a, vv = swp ? a : b;
+  const int kr = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
+  const real *srcL = face + (((int64_t)r.eL * 6 + fL) * 20) * NFP + kk;
+  const real *srcR = face + (((int64_t)r.eR * 6 + fR) * 20) * NFP + kr;
+  const real *fg = fgeo + (fc * 4) * NFP + kk;
+  real UL[5], UR[5], UC[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    UL[v] = srcL[v * NFP];
+    UR[v] = srcR[v * NFP];
+  }
+  const real NL[3] = {fg[0], fg[NFP], fg[2 * NFP]};
+  const real nm = sqrt(NL[0] * NL[0] + NL[1] * NL[1] + NL[2] * NL[2]);
+  const real inm = real(1) / nm;
+  const real nh[3] = {NL[0] * inm, NL[1] * inm, NL[2] * inm};
+#pragma unroll
+  for (int v = 0; v < 5; ++v) UC[v] = real(0.5) * (UL[v] + UR[v]);
+  real Fvn[5] = {0, 0, 0, 0, 0};
+  if (VISC) {
+    // BR2: mean of the broken gradients plus the two face liftings, which combine to
+    // sigma N (U_R - U_L) with N the owner's normal
+    const real sig = fg[3 * NFP];
+    real GI[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        GI[i][v] = real(0.5) * (srcL[(5 + i * 5 + v) * NFP] + srcR[(5 + i * 5 + v) * NFP]) +
+                   sig * NL[i] * (UR[v] - UL[v]);
+    real Fv[3][5];
+    visc_flux(UC, GI, ph, Fv);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fvn[v] = Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
+  }
+  real Fi[5];
+  if (flux == 0) rusanov(UL, UR, nh, ph, Fi);
+  else roe(UL, UR, nh, ph, Fi);
+  real *dst = fout + (fc * 10) * NFP + kk;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    dst[v * NFP] = real(0.5) * (UR[v] - UL[v]);
+    dst[(5 + v) * NFP] = nm * (Fi[v] - Fvn[v]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// K3: volume kernel. Per element: gathers its faces' jumps and common fluxes into LDS, forms
+// the corrected gradient (g_DG correction by U^C - U), the pointwise flux F_inv - F_v, the
+// transformed divergence sum_n D_n F^n plus the flux correction
+// (s F^{I,perp} - F^d_f) g'(xi_d), R = -div/|J|, and the RK register update.
+// ------------------------------------------------------------------------------------------
+template <int P, typename real, bool VISC>
+__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
+    const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
+    const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
+    double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2) {
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
-  constexpr int NG = VISC ? 15 : 0;
-  __shared__ real sU[EPB][5][NS];
-  __shared__ real sG[EPB][NG > 5 ? NG : 5][NS];  // broken gradient, later the transformed flux
-  constexpr int NJU = VISC ? NF : 1;
-  __shared__ real sJU[EPB][5][NJU];              // U^C - U_own at face points
-  __shared__ real sJF[EPB][5][NF];               // common flux along +xi_d, then its jump
+  constexpr int NJ = (VISC ? 10 : 5) * NF;
+  __shared__ real sUall[EPB][5 * NS];  // state, then the transformed flux of one direction
+  __shared__ real sJall[EPB][NJ];      // [5][NF] flux along +xi_d (then its jump); [5][NF] U^C - U
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
   const int idx[3] = {t % N, (t / N) % N, t / (N * N)};
+  real *sU = sUall[slot];
+  real *sJ = sJall[slot];
 
   real U[5];
-  real ja[9];
-  real iJ = 0;
-  real dU[3][5];
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       U[v] = real(X[(e * 5 + v) * NS + t]);
-      sU[slot][v][t] = U[v];
+      sU[v * NS + t] = U[v];
     }
+    // face data of the six faces, seen from this element
+    for (int q = t; q < (VISC ? 10 : 5) * NF; q += NS) {
+      const int comp = q / NF, fp = q - comp * NF;  // comp 0-4: flux, 5-9: jump
+      const int f = fp / NFP, kk = fp - f * NFP;
+      const FaceRef fr = fref[e * 6 + f];
+      const bool owner = (fr.code >> 6) & 1;
+      const int a = kk % N, b = kk / N;
+      const bool swp = (fr.code >> 3) & 1, flu = (fr.code >> 4) & 1, flv = (fr.code >> 5) & 1;
+      const int uu = swp ? b : a, vv = swp ? a : b;
+      const int kc = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
+      const int src_comp = comp < 5 ? 5 + comp : comp - 5;
+      const real val = fout[((int64_t)fr.fid * 10 + src_comp) * NFP + kc];
+      const real sgn = owner ? real(1) : real(-1);
+      sJ[q] = comp < 5 ? ((f & 1) ? sgn : -sgn) * val : sgn * val;
+    }
+  }
+  __syncthreads();
+  real F[3][5];
+  real ja[9];
+  real iJ = 0;
+  if (act) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
     iJ = geo[(e * 10 + 9) * NS + t];
-  }
-  __syncthreads();
-  // ---- phase A: reference gradient and broken physical gradient ----
-  if (VISC && act) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      real d0 = 0, d1 = 0, d2 = 0;
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        d0 += ops.D[idx[0] * N + c] * sU[slot][v][c + N * (idx[1] + N * idx[2])];
-        d1 += ops.D[idx[1] * N + c] * sU[slot][v][idx[0] + N * (c + N * idx[2])];
-        d2 += ops.D[idx[2] * N + c] * sU[slot][v][idx[0] + N * (idx[1] + N * c)];
-      }
-      dU[0][v] = d0;
-      dU[1][v] = d1;
-      dU[2][v] = d2;
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) {
-        real g = ja[ii] * d0;
-        g += ja[3 + ii] * d1;
-        g += ja[6 + ii] * d2;
-        sG[slot][ii * 5 + v][t] = iJ * g;
-      }
-    }
-  }
-  __syncthreads();
-  // ---- phase B: common state and common normal flux at every face point ----
-  if (act) {
-    for (int fp = t; fp < NF; fp += NS) {
-      const int f = fp / NFP, kk = fp - f * NFP;
-      const int a = kk % N, b = kk / N, d = f >> 1;
-      const real *ell = (f & 1) ? ops.lp : ops.lm;
-      real uo[5], un[5];
-      real go[VISC ? 15 : 1], gn[VISC ? 15 : 1];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        real acc = 0;
-#pragma unroll
-        for (int c = 0; c < N; ++c) acc += ell[c] * sU[slot][v][line_pt<N>(d, c, a, b)];
-        uo[v] = acc;
-      }
-      if (VISC) {
-#pragma unroll
-        for (int g = 0; g < 15; ++g) {
-          real acc = 0;
-#pragma unroll
-          for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][g][line_pt<N>(d, c, a, b)];
-          go[g] = acc;
-        }
-      }
-      const FaceConn cn = conn[e * 6 + f];
-      const int code = cn.code;
-      const int fn = code & 7;
-      const bool swp = (code >> 3) & 1, flu = (code >> 4) & 1, flv = (code >> 5) & 1, owner = (code >> 6) & 1;
-      const int uu = swp ? b : a, vv = swp ? a : b;
-      const int kn = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
-      const real *src = face + (((int64_t)cn.nbr * 6 + fn) * 20) * NFP + kn;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) un[v] = src[v * NFP];
-      if (VISC) {
-#pragma unroll
-        for (int g = 0; g < 15; ++g) gn[g] = src[(5 + g) * NFP];
-      }
-      const real *fg = fgeo + ((e * 6 + f) * 4) * NFP + kk;
-      real NL[3] = {fg[0], fg[NFP], fg[2 * NFP]};
-      if (!owner) {
-        NL[0] = -NL[0];
-        NL[1] = -NL[1];
-        NL[2] = -NL[2];
-      }
-      const real nm = sqrt(NL[0] * NL[0] + NL[1] * NL[1] + NL[2] * NL[2]);
-      const real inm = real(1) / nm;
-      const real nh[3] = {NL[0] * inm, NL[1] * inm, NL[2] * inm};
-      real UL[5], UR[5], UC[5], Fi[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        UL[v] = owner ? uo[v] : un[v];
-        UR[v] = owner ? un[v] : uo[v];
-        UC[v] = real(0.5) * (UL[v] + UR[v]);
-      }
-      if (flux == 0) rusanov(UL, UR, nh, ph, Fi);
-      else roe(UL, UR, nh, ph, Fi);
-      if (VISC) {
-        const real sig = fg[3 * NFP];
-        real GI[3][5];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int v = 0; v < 5; ++v)
-            GI[i][v] = real(0.5) * (go[i * 5 + v] + gn[i * 5 + v]) + sig * NL[i] * (UR[v] - UL[v]);
-        real Fv[3][5];
-        visc_flux(UC, GI, ph, Fv);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) Fi[v] -= Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
-      }
-      // owner: F^{I,perp}_own = nm Fi; other side: -nm Fi. Stored along +xi_d: times s.
-      const real sg = ((f & 1) ? real(1) : real(-1)) * (owner ? real(1) : real(-1));
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        sJF[slot][v][fp] = sg * (nm * Fi[v]);
-        if (VISC) sJU[slot][v][fp % NJU] = UC[v] - uo[v];
-      }
-    }
-  }
-  __syncthreads();
-  // ---- phase C: corrected gradient and pointwise flux ----
-  real F[3][5];
-  if (act) {
-    if (VISC) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
-        const int kk = idx[u] + N * idx[w];
-        const real cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
-          dU[d][v] += sJU[slot][v][((2 * d) * NFP + kk) % NJU] * cL + sJU[slot][v][((2 * d + 1) * NFP + kk) % NJU] * cR;
-      }
-    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const real ei[3] = {real(i == 0), real(i == 1), real(i == 2)};
@@ -409,6 +373,29 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_element(
       flux_n(U, ei, ph, F[i], un_, c_);
     }
     if (VISC) {
+      real dU[3][5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        real d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+          d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+          d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+        }
+        dU[0][v] = d0;
+        dU[1][v] = d1;
+        dU[2][v] = d2;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
+        const int kk = idx[u] + N * idx[w];
+        const real cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          dU[d][v] += sJ[(5 + v) * NF + (2 * d) * NFP + kk] * cL + sJ[(5 + v) * NF + (2 * d + 1) * NFP + kk] * cR;
+      }
       real G[3][5];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -427,14 +414,16 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_element(
         for (int v = 0; v < 5; ++v) F[i][v] -= Fv[i][v];
     }
   }
-  // ---- phase D: divergence of the transformed flux and the flux correction, per direction ----
+  // divergence of the transformed flux and the flux correction, one direction at a time
   real div[5] = {0, 0, 0, 0, 0};
+  real *sF = sU;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    __syncthreads();  // previous users of sG / sJF are done
+    __syncthreads();
     if (act) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sG[slot][v][t] = ja[d * 3 + 0] * F[0][v] + ja[d * 3 + 1] * F[1][v] + ja[d * 3 + 2] * F[2][v];
+      for (int v = 0; v < 5; ++v)
+        sF[v * NS + t] = ja[d * 3 + 0] * F[0][v] + ja[d * 3 + 1] * F[1][v] + ja[d * 3 + 2] * F[2][v];
     }
     __syncthreads();
     if (act) {
@@ -443,9 +432,9 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_element(
         real acc = 0;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          int id2[3] = {idx[0], idx[1], idx[2]};
-          id2[d] = c;
-          acc += ops.D[idx[d] * N + c] * sG[slot][v][id2[0] + N * (id2[1] + N * id2[2])];
+          const int id = d == 0 ? c + N * (idx[1] + N * idx[2])
+                                : (d == 1 ? idx[0] + N * (c + N * idx[2]) : idx[0] + N * (idx[1] + N * c));
+          acc += ops.D[idx[d] * N + c] * sF[v * NS + id];
         }
         div[v] += acc;
       }
@@ -457,8 +446,8 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_element(
         for (int v = 0; v < 5; ++v) {
           real acc = 0;
 #pragma unroll
-          for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][v][line_pt<N>(d, c, a, b)];
-          sJF[slot][v][f * NFP + kk] -= acc;
+          for (int c = 0; c < N; ++c) acc += ell[c] * sF[v * NS + line_pt<N>(d, c, a, b)];
+          sJ[v * NF + f * NFP + kk] -= acc;
         }
       }
     }
@@ -468,12 +457,11 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_element(
       const int kk = idx[u] + N * idx[w];
       const real cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        div[v] += sJF[slot][v][(2 * d) * NFP + kk] * cL + sJF[slot][v][(2 * d + 1) * NFP + kk] * cR;
+      for (int v = 0; v < 5; ++v) div[v] += sJ[v * NF + (2 * d) * NFP + kk] * cL + sJ[v * NF + (2 * d + 1) * NFP + kk] * cR;
     }
   }
   if (!act) return;
-  // ---- R = -div / |J| and the RK register update ----
+  // R = -div / |J| and the RK register update
   const int64_t base = e * 5 * NS + t;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -533,9 +521,10 @@ static int fail(int code, const std::string &msg) {
 
 static bool valid(fr_mesh_t m) { return m != nullptr && m->magic == kMagic; }
 
+// ms (optional): accumulates the durations of the three kernels, measured with HIP events.
 template <int P, typename real, bool VISC>
 static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
-                          float *k1_ms, float *k3_ms) {
+                          double *ms) {
   using C = Cfg<P>;
   OpsT<real> ops;
   for (int i = 0; i < kMaxN * kMaxN; ++i) ops.D[i] = real(dm.ops.D[i]);
@@ -547,52 +536,58 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
   }
   Phys<real> ph{real(dm.phys.gamma), real(dm.phys.gamma - 1.0), real(dm.phys.mu), real(dm.phys.kappa)};
   const int64_t blocks = (dm.E + C::EPB - 1) / C::EPB;
+  const int64_t fblocks = (dm.F * C::NFP + 255) / 256;
   hipStream_t s = (hipStream_t)dm.stream;
-  hipEvent_t ev[3];
-  const bool timed = k1_ms != nullptr;
-  if (timed) {
-    for (int i = 0; i < 3; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  hipEvent_t ev[4];
+  if (ms) {
+    for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], s));
   }
   hipLaunchKernelGGL((k_prepass<P, real, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
                      (const real *)dm.geo, (real *)dm.face, dm.E, ops);
   HIPCHK(hipGetLastError());
-  if (timed) HIPCHK(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL((k_element<P, real, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
-                     (const real *)dm.geo, (const real *)dm.fgeo, dm.conn, (const real *)dm.face, dm.E, ops, ph,
-                     dm.flux, st, out0, reg1, reg2);
+  if (ms) HIPCHK(hipEventRecord(ev[1], s));
+  hipLaunchKernelGGL((k_face<P, real, VISC>), dim3((unsigned)fblocks), dim3(256), 0, s, (const real *)dm.face,
+                     (const real *)dm.fgeo, dm.ftab, dm.F, ph, dm.flux, (real *)dm.fout);
   HIPCHK(hipGetLastError());
-  if (timed) {
-    HIPCHK(hipEventRecord(ev[2], s));
-    HIPCHK(hipEventSynchronize(ev[2]));
-    HIPCHK(hipEventElapsedTime(k1_ms, ev[0], ev[1]));
-    HIPCHK(hipEventElapsedTime(k3_ms, ev[1], ev[2]));
-    for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+  if (ms) HIPCHK(hipEventRecord(ev[2], s));
+  hipLaunchKernelGGL((k_volume<P, real, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+                     (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1, reg2);
+  HIPCHK(hipGetLastError());
+  if (ms) {
+    HIPCHK(hipEventRecord(ev[3], s));
+    HIPCHK(hipEventSynchronize(ev[3]));
+    for (int i = 0; i < 3; ++i) {
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[i] += t;
+    }
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
   }
   return FR_OK;
 }
 
 template <typename real, bool VISC>
 static int launch_stage_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
-                          float *t1, float *t3) {
+                          double *ms) {
   switch (dm.p) {
-    case 0: return launch_stage_t<0, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
-    case 1: return launch_stage_t<1, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
-    case 2: return launch_stage_t<2, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
-    case 3: return launch_stage_t<3, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
-    case 4: return launch_stage_t<4, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
-    case 5: return launch_stage_t<5, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
-    case 6: return launch_stage_t<6, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
-    case 7: return launch_stage_t<7, real, VISC>(dm, X, st, o, r1, r2, t1, t3);
+    case 0: return launch_stage_t<0, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 1: return launch_stage_t<1, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 2: return launch_stage_t<2, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 3: return launch_stage_t<3, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 4: return launch_stage_t<4, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 5: return launch_stage_t<5, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 6: return launch_stage_t<6, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 7: return launch_stage_t<7, real, VISC>(dm, X, st, o, r1, r2, ms);
     default: return fail(FR_ERR_UNSUPPORTED, "p out of range");
   }
 }
 
 static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
-                        float *t1 = nullptr, float *t3 = nullptr) {
+                        double *ms = nullptr) {
   if (dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "only FR_FP64 is built in this path");
-  return dm.viscous ? launch_stage_p<double, true>(dm, X, st, o, r1, r2, t1, t3)
-                    : launch_stage_p<double, false>(dm, X, st, o, r1, r2, t1, t3);
+  return dm.viscous ? launch_stage_p<double, true>(dm, X, st, o, r1, r2, ms)
+                    : launch_stage_p<double, false>(dm, X, st, o, r1, r2, ms);
 }
 
 // Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients.
@@ -605,8 +600,6 @@ static const double kLsB[5] = {1432997174477.0 / 9575080441237.0, 5161836677717.
 static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms_acc) {
   DeviceMesh &dm = m->dm;
   const int64_t M = dm.E * 5 * dm.Ns;
-  float t1 = 0, t3 = 0;
-  float *p1 = ms_acc ? &t1 : nullptr, *p3 = ms_acc ? &t3 : nullptr;
   for (int step = 0; step < n_steps; ++step) {
     if (scheme == FR_LSRK45) {
       if (!dm.R1) {
@@ -620,9 +613,9 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
         st.a = kLsA[s];
         st.b = kLsB[s];
         st.dt = dt;
-        int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, p1, p3);
+        int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, ms_acc);
         if (rc) return rc;
-        if (ms_acc) { ms_acc[0] += t1; ms_acc[1] += t3; ms_acc[2] += 1; }
+        if (ms_acc) ms_acc[3] += 1;
       }
     } else if (scheme == FR_RK4) {
       if (!dm.R1) {
@@ -644,9 +637,9 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
         st.cdt = c[s] * dt;
         st.dt = dt;
         const double *X = s == 0 ? dm.U : dm.R2;
-        int rc = launch_stage(dm, X, st, dm.U, dm.R1, dm.R2, p1, p3);
+        int rc = launch_stage(dm, X, st, dm.U, dm.R1, dm.R2, ms_acc);
         if (rc) return rc;
-        if (ms_acc) { ms_acc[0] += t1; ms_acc[1] += t3; ms_acc[2] += 1; }
+        if (ms_acc) ms_acc[3] += 1;
       }
     } else {
       return fail(FR_ERR_ARG, "unknown scheme");
@@ -707,9 +700,12 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   int rc = FR_OK;
   if (!rc) rc = alloc((void **)&dm.U, M * sizeof(double));
   if (!rc) rc = alloc(&dm.geo, H.geo.size() * sizeof(double));
+  dm.F = (int64_t)H.ftab.size();
   if (!rc) rc = alloc(&dm.fgeo, H.fgeo.size() * sizeof(double));
-  if (!rc) rc = alloc((void **)&dm.conn, H.conn.size() * sizeof(FaceConn));
+  if (!rc) rc = alloc((void **)&dm.ftab, H.ftab.size() * sizeof(FaceRec));
+  if (!rc) rc = alloc((void **)&dm.fref, H.fref.size() * sizeof(FaceRef));
   if (!rc) rc = alloc(&dm.face, (size_t)dm.E * 6 * 20 * dm.Nfp * sizeof(double));
+  if (!rc) rc = alloc(&dm.fout, (size_t)dm.F * 10 * dm.Nfp * sizeof(double));
   if (!rc) rc = alloc((void **)&dm.flag, sizeof(int));
   if (rc) {
     fr_mesh_destroy(m);
@@ -718,7 +714,9 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t e1 = hipMemcpyAsync(dm.geo, H.geo.data(), H.geo.size() * sizeof(double), hipMemcpyHostToDevice, s);
   hipError_t e2 = hipMemcpyAsync(dm.fgeo, H.fgeo.data(), H.fgeo.size() * sizeof(double), hipMemcpyHostToDevice, s);
-  hipError_t e3 = hipMemcpyAsync(dm.conn, H.conn.data(), H.conn.size() * sizeof(FaceConn), hipMemcpyHostToDevice, s);
+  hipError_t e3 = hipMemcpyAsync(dm.ftab, H.ftab.data(), H.ftab.size() * sizeof(FaceRec), hipMemcpyHostToDevice, s);
+  if (e3 == hipSuccess)
+    e3 = hipMemcpyAsync(dm.fref, H.fref.data(), H.fref.size() * sizeof(FaceRef), hipMemcpyHostToDevice, s);
   hipError_t e4 = hipMemsetAsync(dm.U, 0, M * sizeof(double), s);
   hipError_t e5 = hipStreamSynchronize(s);  // host vectors die at return
   if (e1 || e2 || e3 || e4 || e5) {
@@ -730,7 +728,8 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   return FR_OK;
 }
 
-int fr_mesh_geometry_host(const fr_mesh_desc *d, double *geo, double *fgeo, int32_t *conn, double *xyz) {
+int fr_mesh_geometry_host(const fr_mesh_desc *d, double *geo, double *fgeo, int32_t *ftab, int32_t *conn,
+                          double *xyz) {
   if (!d || !d->elem_vert || !d->elem_nodes) return fail(FR_ERR_ARG, "NULL descriptor or arrays");
   if (d->p < 0 || d->p > kMaxP) return fail(FR_ERR_ARG, "p must be in 0..7");
   if (d->q < 1 || d->q > (d->p > 1 ? d->p : 1)) return fail(FR_ERR_ARG, "q must be in 1..max(p,1)");
@@ -739,7 +738,9 @@ int fr_mesh_geometry_host(const fr_mesh_desc *d, double *geo, double *fgeo, int3
   std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->br2_eta, H);
   if (!err.empty()) return fail(FR_ERR_MESH, err);
   if (geo) std::memcpy(geo, H.geo.data(), H.geo.size() * sizeof(double));
+  if (H.ftab.size() != (size_t)d->n_elem * 3) return fail(FR_ERR_MESH, "face count is not 3 n_elem");
   if (fgeo) std::memcpy(fgeo, H.fgeo.data(), H.fgeo.size() * sizeof(double));
+  if (ftab) std::memcpy(ftab, H.ftab.data(), H.ftab.size() * sizeof(FaceRec));
   if (conn) std::memcpy(conn, H.conn.data(), H.conn.size() * sizeof(FaceConn));
   if (xyz) std::memcpy(xyz, H.xyz.data(), H.xyz.size() * sizeof(double));
   return FR_OK;
@@ -751,7 +752,7 @@ int fr_mesh_destroy(fr_mesh_t m) {
   DeviceMesh &dm = m->dm;
   if (dm.stream) (void)hipStreamSynchronize((hipStream_t)dm.stream);
   else (void)hipDeviceSynchronize();
-  void *bufs[] = {dm.U, dm.R1, dm.R2, dm.geo, dm.fgeo, dm.conn, dm.face, dm.flag};
+  void *bufs[] = {dm.U, dm.R1, dm.R2, dm.geo, dm.fgeo, dm.ftab, dm.fref, dm.face, dm.fout, dm.flag};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   m->magic = 0;
@@ -842,11 +843,10 @@ int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_b
 
 int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms) {
   if (!valid(m) || !ms) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
-  double acc[3] = {0, 0, 0};
+  double acc[4] = {0, 0, 0, 0};
   int rc = run_steps(m, dt, scheme, n_steps, acc);
   if (rc) return rc;
-  ms[0] = acc[2] > 0 ? acc[0] / acc[2] : 0;
-  ms[1] = acc[2] > 0 ? acc[1] / acc[2] : 0;
+  for (int i = 0; i < 3; ++i) ms[i] = acc[3] > 0 ? acc[i] / acc[3] : 0;
   return FR_OK;
 }
 

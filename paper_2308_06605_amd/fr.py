@@ -63,7 +63,7 @@ def load():
     L.fr_rk_step.argtypes = [P, f64, i32, i32]
     L.fr_mesh_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
     L.fr_profile_stages.argtypes = [P, f64, i32, i32, P]
-    L.fr_mesh_geometry_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, P, P, P]
+    L.fr_mesh_geometry_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, P, P, P, P]
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
                  "fr_mesh_geometry_host"):
@@ -94,17 +94,18 @@ def _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep):
 
 
 def geometry_host(mesh, p: int, eta: float = 6.0):
-    """Host-only mesh setup (fr_mesh_geometry_host): geo, fgeo, conn, xyz as numpy arrays."""
+    """Host-only mesh setup (fr_mesh_geometry_host): geo, fgeo, ftab, conn, xyz as numpy arrays."""
     keep = []
     d = _desc(mesh, p, 0.0, 1.4, 0.72, eta, "rusanov", "fp64", False, keep)
     E, Ns, Nfp = d.n_elem, (p + 1) ** 3, (p + 1) ** 2
     geo = np.empty((E, 10, Ns))
-    fgeo = np.empty((E, 6, 4, Nfp))
+    fgeo = np.empty((3 * E, 4, Nfp))
+    ftab = np.empty((3 * E, 4), dtype=np.int32)
     conn = np.empty((E, 6, 2), dtype=np.int32)
     xyz = np.empty((E, 3, Ns))
     _check(load().fr_mesh_geometry_host(ctypes.byref(d), geo.ctypes.data, fgeo.ctypes.data,
-                                        conn.ctypes.data, xyz.ctypes.data))
-    return geo, fgeo, conn, xyz
+                                        ftab.ctypes.data, conn.ctypes.data, xyz.ctypes.data))
+    return geo, fgeo, ftab, conn, xyz
 
 
 class FRMesh:
@@ -179,9 +180,10 @@ class FRMesh:
         _check(load().fr_rk_step(self.h, float(dt), SCHEME[scheme], int(n_steps)))
 
     def profile_stages(self, dt: float, scheme: str = "lsrk45", n_steps: int = 1):
-        ms = np.zeros(2)
+        """Mean ms per stage of (pre-pass, face, volume) kernels, from HIP events."""
+        ms = np.zeros(3)
         _check(load().fr_profile_stages(self.h, float(dt), SCHEME[scheme], int(n_steps), ms.ctypes.data))
-        return float(ms[0]), float(ms[1])
+        return tuple(float(x) for x in ms)
 
     def info(self):
         E, ns, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()

@@ -32,7 +32,7 @@ def test_host_setup_matches_oracle(n, p, q, scramble):
     m = I.box_mesh(n, q=q, curve_amp=0.05 if p > 0 else 0.0, curve_mode="mixed")
     if scramble:
         m, _ = I.scramble_mesh(m, seed=3)
-    geo, fgeo, conn, xyz = fr.geometry_host(m, p)
+    geo, fgeo, ftab, conn, xyz = fr.geometry_host(m, p)
     o = oracle.Oracle(m, p)
     Ja, dJ, Nf, _ = o.geometry()
     nbr, nface, owner, perm = o.connectivity()
@@ -45,7 +45,14 @@ def test_host_setup_matches_oracle(n, p, q, scramble):
     assert np.array_equal(conn[:, :, 0], nbr)
     assert np.array_equal(conn[:, :, 1] & 7, nface)
     assert np.array_equal((conn[:, :, 1] >> 6) & 1, owner)
-    assert np.abs(np.transpose(fgeo[:, :, :3, :], (0, 1, 3, 2)) - Nf).max() < 4e-15 * scale
+    # face records: owner element/face in order, normal from the owner's metrics
+    owners = [(e, f) for e in range(E) for f in range(6) if owner[e, f]]
+    assert len(owners) == ftab.shape[0] == 3 * E
+    for fid, (e, f) in enumerate(owners):
+        assert ftab[fid, 0] == e and (ftab[fid, 2] & 7) == f
+        assert ftab[fid, 1] == nbr[e, f] and ((ftab[fid, 2] >> 3) & 7) == nface[e, f]
+        assert ((ftab[fid, 2] >> 6) & 7) == ((conn[e, f, 1] >> 3) & 7)
+        assert np.abs(fgeo[fid, :3, :].T - Nf[e, f]).max() < 4e-15 * scale
     N1 = p + 1
     code = conn[:, :, 1]
     for e in range(E):
