@@ -335,37 +335,67 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
   real *sU = sUall[slot];
   real *sJ = sJall[slot];
 
-  real U[5];
+  // every global load is issued here, before the first barrier: the state, the metric terms,
+  // the RK registers and this element's share of its faces' jumps and fluxes
+  constexpr int R = (NF + NS - 1) / NS;  // face points per thread
+  constexpr int NC = VISC ? 10 : 5;
+  real U[5], ja[9], iJ = 0;
+  double Xd[5], r1[5], r2[5];
+  real gv[R][NC];
+  const int64_t base = e * 5 * NS + t;
   if (act) {
 #pragma unroll
+    for (int v = 0; v < 5; ++v) Xd[v] = X[base + v * NS];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
+    iJ = geo[(e * 10 + 9) * NS + t];
+    if (st.mode == kModeLSRK) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+    } else if (st.mode == kModeRK4) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+        r2[v] = out0[base + v * NS];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int fp = t + r * NS;
+      if (fp < NF) {
+        const int f = fp / NFP, kk = fp - f * NFP;
+        const FaceRef fr = fref[e * 6 + f];
+        const int a = kk % N, b = kk / N;
+        const bool swp = (fr.code >> 3) & 1, flu = (fr.code >> 4) & 1, flv = (fr.code >> 5) & 1;
+        const int uu = swp ? b : a, vv = swp ? a : b;
+        const int kc = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
+        const real *src = fout + ((int64_t)fr.fid * 10) * NFP + kc;
+        const real sgn = ((fr.code >> 6) & 1) ? real(1) : real(-1);
+        const real sfl = (f & 1) ? sgn : -sgn;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          // c < 5: owner's flux -> s F^{I,perp}_own; c >= 5: jump -> U^C - U_own
+          gv[r][c] = c < 5 ? sfl * src[(5 + c) * NFP] : sgn * src[(c - 5) * NFP];
+        }
+      }
+    }
+#pragma unroll
     for (int v = 0; v < 5; ++v) {
-      U[v] = real(X[(e * 5 + v) * NS + t]);
+      U[v] = real(Xd[v]);
       sU[v * NS + t] = U[v];
     }
-    // face data of the six faces, seen from this element
-    for (int q = t; q < (VISC ? 10 : 5) * NF; q += NS) {
-      const int comp = q / NF, fp = q - comp * NF;  // comp 0-4: flux, 5-9: jump
-      const int f = fp / NFP, kk = fp - f * NFP;
-      const FaceRef fr = fref[e * 6 + f];
-      const bool owner = (fr.code >> 6) & 1;
-      const int a = kk % N, b = kk / N;
-      const bool swp = (fr.code >> 3) & 1, flu = (fr.code >> 4) & 1, flv = (fr.code >> 5) & 1;
-      const int uu = swp ? b : a, vv = swp ? a : b;
-      const int kc = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
-      const int src_comp = comp < 5 ? 5 + comp : comp - 5;
-      const real val = fout[((int64_t)fr.fid * 10 + src_comp) * NFP + kc];
-      const real sgn = owner ? real(1) : real(-1);
-      sJ[q] = comp < 5 ? ((f & 1) ? sgn : -sgn) * val : sgn * val;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int fp = t + r * NS;
+      if (fp < NF) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sJ[c * NF + fp] = gv[r][c];
+      }
     }
   }
   __syncthreads();
   real F[3][5];
-  real ja[9];
-  real iJ = 0;
   if (act) {
-#pragma unroll
-    for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
-    iJ = geo[(e * 10 + 9) * NS + t];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const real ei[3] = {real(i == 0), real(i == 1), real(i == 2)};
@@ -462,7 +492,6 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
   }
   if (!act) return;
   // R = -div / |J| and the RK register update
-  const int64_t base = e * 5 * NS + t;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const double R = -double(div[v]) * double(iJ);
@@ -470,18 +499,18 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
     if (st.mode == kModeResidual) {
       out0[o] = R;
     } else if (st.mode == kModeLSRK) {
-      // out0 = U (read and written), reg1 = dU
-      const double du = (st.first ? 0.0 : st.a * reg1[o]) + st.dt * R;
+      // out0 = U (the state this stage was evaluated on, Xd), reg1 = dU
+      const double du = st.a * r1[v] + st.dt * R;
       reg1[o] = du;
-      out0[o] = out0[o] + st.b * du;
+      out0[o] = Xd[v] + st.b * du;
     } else {
-      // RK4: out0 = Q, reg1 = accumulator, reg2 = stage state S
-      const double acc = (st.first ? 0.0 : reg1[o]) + st.w * R;
+      // RK4: out0 = Q (r2), reg1 = accumulator (r1), reg2 = stage state S
+      const double acc = r1[v] + st.w * R;
       if (!st.last) {
         reg1[o] = acc;
-        reg2[o] = out0[o] + st.cdt * R;
+        reg2[o] = r2[v] + st.cdt * R;
       } else {
-        out0[o] = out0[o] + st.dt * acc;
+        out0[o] = r2[v] + st.dt * acc;
       }
     }
   }
