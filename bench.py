@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--scheme", default="lsrk45")
     ap.add_argument("--dt", type=float, default=2.5e-4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-sized device buffer once (a known-size "
+                         "dispatch that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -191,6 +194,14 @@ def main():
         "wall_s_timed": t_wall,
         "finite": ok,
     }
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = n * 8
     print(json.dumps(out), flush=True)
 
 

@@ -161,6 +161,19 @@ struct Cfg {
   static constexpr int BLOCK = EPB * NS;
 };
 
+// Occupancy targets (waves per SIMD) per kernel and degree; 0 lets the compiler decide. Forcing
+// more waves than the compiler picks spilled to scratch (HBM traffic) in every measured case.
+#ifndef FR_WPE_PREPASS
+#define FR_WPE_PREPASS(P) 0
+#endif
+#ifndef FR_WPE_FACE
+#define FR_WPE_FACE(P) 0
+#endif
+#ifndef FR_WPE_VOLUME
+#define FR_WPE_VOLUME(P) 0
+#endif
+#define FR_WPE_ATTR(w) __attribute__((amdgpu_waves_per_eu((w) > 0 ? (w) : 1, (w) > 0 ? 8 : 8)))
+
 template <typename real>
 struct OpsT {
   real D[kMaxN * kMaxN];
@@ -181,7 +194,7 @@ __device__ __forceinline__ int line_pt(int d, int c, int a, int b) {
 // K1: element pre-pass
 // ------------------------------------------------------------------------------------------
 template <int P, typename real, bool VISC>
-__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass(const double *__restrict__ X,
+__global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void k_prepass(const double *__restrict__ X,
                                                            const real *__restrict__ geo,
                                                            real *__restrict__ face, int64_t E,
                                                            OpsT<real> ops) {
@@ -204,7 +217,8 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass(const double *__restr
 #pragma unroll
     for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
     const real iJ = geo[(e * 10 + 9) * NS + t];
-#pragma unroll
+    constexpr int UNV = P >= 6 ? 1 : 5;  // bounds the loads in flight at high degree
+#pragma unroll UNV
     for (int v = 0; v < 5; ++v) {
       real d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
@@ -224,26 +238,26 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass(const double *__restr
   }
   __syncthreads();
   if (!act) return;
-  for (int fp = t; fp < NF; fp += NS) {
+  // items are (group of GV values, face point); consecutive threads write consecutive points
+  // of one face. With more face points than threads (p <= 4) one item carries all 20 values,
+  // which amortises the index arithmetic; at higher degree groups of 5 balance the threads.
+  constexpr int NVAL = VISC ? 20 : 5;
+  constexpr int GV = (NF > NS || !VISC) ? NVAL : 5;
+  constexpr int NGRP = NVAL / GV;
+  for (int q = t; q < NGRP * NF; q += NS) {
+    const int grp = q / NF, fp = q - grp * NF;
     const int f = fp / NFP, kk = fp - f * NFP;
     const int a = kk % N, b = kk / N, d = f >> 1;
     const real *ell = (f & 1) ? ops.lp : ops.lm;
-    real *dst = face + ((e * 6 + f) * 20) * NFP + kk;
+    real *dst = face + ((e * 6 + f) * 20 + GV * grp) * NFP + kk;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < GV; ++v) {
+      const int val = GV * grp + v;
+      const real *src = val < 5 ? &sU[slot][val][0] : &sG[slot][(val - 5) % (NG > 0 ? NG : 1)][0];
       real acc = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) acc += ell[c] * sU[slot][v][line_pt<N>(d, c, a, b)];
+      for (int c = 0; c < N; ++c) acc += ell[c] * src[line_pt<N>(d, c, a, b)];
       dst[v * NFP] = acc;
-    }
-    if (VISC) {
-#pragma unroll
-      for (int g = 0; g < 15; ++g) {
-        real acc = 0;
-#pragma unroll
-        for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][g][line_pt<N>(d, c, a, b)];
-        dst[(5 + g) * NFP] = acc;
-      }
     }
   }
 }
@@ -255,7 +269,7 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass(const double *__restr
 // F^{I,perp}_L = |N| (F*_inv - F_v(U^C, G^I) . n) to a face-major buffer [F][10][Nfp].
 // ------------------------------------------------------------------------------------------
 template <int P, typename real, bool VISC>
-__global__ __launch_bounds__(256) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
+__global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
                                               const FaceRec *__restrict__ ftab, int64_t F, Phys<real> ph,
                                               int flux, real *__restrict__ fout) {
   constexpr int N = P + 1, NFP = N * N;
@@ -319,7 +333,7 @@ __global__ __launch_bounds__(256) void k_face(const real *__restrict__ face, con
 // (s F^{I,perp} - F^d_f) g'(xi_d), R = -div/|J|, and the RK register update.
 // ------------------------------------------------------------------------------------------
 template <int P, typename real, bool VISC>
-__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
+__global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k_volume(
     const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
     double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2) {
@@ -349,16 +363,6 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
 #pragma unroll
     for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
     iJ = geo[(e * 10 + 9) * NS + t];
-    if (st.mode == kModeLSRK) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) r1[v] = st.first ? 0.0 : reg1[base + v * NS];
-    } else if (st.mode == kModeRK4) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        r1[v] = st.first ? 0.0 : reg1[base + v * NS];
-        r2[v] = out0[base + v * NS];
-      }
-    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int fp = t + r * NS;
@@ -444,6 +448,29 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
         for (int v = 0; v < 5; ++v) F[i][v] -= Fv[i][v];
     }
   }
+  // transformed flux F^d = sum_i Ja[d][i] F_i for the three directions; the metric terms are
+  // not needed after this
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const real f0 = F[0][v], f1 = F[1][v], f2 = F[2][v];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) F[d][v] = ja[d * 3 + 0] * f0 + ja[d * 3 + 1] * f1 + ja[d * 3 + 2] * f2;
+    }
+  }
+  // the RK registers are loaded here so that their latency overlaps the divergence phase
+  if (act) {
+    if (st.mode == kModeLSRK) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+    } else if (st.mode == kModeRK4) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+        r2[v] = out0[base + v * NS];
+      }
+    }
+  }
   // divergence of the transformed flux and the flux correction, one direction at a time
   real div[5] = {0, 0, 0, 0, 0};
   real *sF = sU;
@@ -452,8 +479,7 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume(
     __syncthreads();
     if (act) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        sF[v * NS + t] = ja[d * 3 + 0] * F[0][v] + ja[d * 3 + 1] * F[1][v] + ja[d * 3 + 2] * F[2][v];
+      for (int v = 0; v < 5; ++v) sF[v * NS + t] = F[d][v];
     }
     __syncthreads();
     if (act) {
