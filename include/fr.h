@@ -137,6 +137,11 @@ int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *m
 int fr_mesh_geometry_host(const fr_mesh_desc *desc, double *geo, double *fgeo, int32_t *ftab, int32_t *conn,
                           double *xyz);
 
+/* Host-only: the 1-D operator tables of degree p (0..7) the kernels use, each of n = p+1
+ * doubles except D (n*n, row-major D[a*n+b] = l_b'(x_a)): lm = l_b(-1), lp = l_b(+1),
+ * gcL = g_L'(x_a) and gcR = g_R'(x_a) of the DG-equivalent correction functions. */
+int fr_basis_host(int p, double *D, double *lm, double *lp, double *gcL, double *gcR);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *fr_last_error(void);
 

@@ -45,7 +45,8 @@ def _load():
     i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
     L.ora_last_error.restype = ctypes.c_char_p
     L.ora_create.restype = P
-    L.ora_create.argtypes = [i32, i32, i64, P, i32, P, f64, f64, f64, f64, i32, i32, i64, P, i32]
+    L.ora_create.argtypes = [i32, i32, i64, P, i32, P, f64, f64, f64, f64, i32, i32, i64, P, i32,
+                             ctypes.c_uint64]
     L.ora_destroy.argtypes = [P]
     for name in ("ora_residual", "ora_sol_coords"):
         getattr(L, name).argtypes = [P, P] if name == "ora_sol_coords" else [P, P, P]
@@ -74,11 +75,15 @@ class Oracle:
     active     : optional element subset whose residual is returned (all by default)
     metric     : "curl" (conservative curl form) or "cross" (cross-product form, a negative
                  control for the freestream test)
+    metric_jitter : non-zero seed: each rounded metric term moves by -1, 0 or +1 unit in the
+                 last place. A test knob that measures how much two implementations which round
+                 the same long-double metric terms independently may differ; 0 = exact rounding.
     """
 
     def __init__(self, mesh, p: int, *, mu: float = 0.0, gamma: float = 1.4,
                  prandtl: float = 0.72, eta: float = 6.0, flux: str = "rusanov",
-                 precision: str = "f64", active=None, metric: str = "curl", nthreads: int = 0):
+                 precision: str = "f64", active=None, metric: str = "curl", nthreads: int = 0,
+                 metric_jitter: int = 0):
         L = _load()
         self.p = p
         self.n = p + 1
@@ -98,7 +103,8 @@ class Oracle:
         self.nthreads = int(nthreads)
         self.h = L.ora_create(PREC[precision], p, self.E, _ptr(self._ev), int(mesh.q),
                               _ptr(self._nodes), gamma, prandtl, mu, eta, FLUX[flux],
-                              {"curl": 0, "cross": 1}[metric], nact, act_ptr, self.nthreads)
+                              {"curl": 0, "cross": 1}[metric], nact, act_ptr, self.nthreads,
+                              int(metric_jitter))
         if not self.h:
             raise RuntimeError("oracle: " + L.ora_last_error().decode())
 

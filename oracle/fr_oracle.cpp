@@ -444,6 +444,9 @@ struct Oracle : Iface {
   T eta;
   int flux;         // 0 Rusanov, 1 Roe
   int metric_form;  // 0 curl form (freestream preserving); 1 cross-product (negative control)
+  uint64_t jitter;  // non-zero: move each rounded metric term by -1, 0 or +1 unit in the last
+                    // place (seeded); measures the residual's sensitivity to independently
+                    // rounded metric terms (a test knob, never part of the method)
   vector<int64_t> active;  // elements whose residual is returned
   vector<char> need;       // elements whose face data is needed (active + neighbours)
   vector<int64_t> slot;    // element -> geometry slot, -1 if not stored
@@ -470,6 +473,20 @@ struct Oracle : Iface {
   }
 
   std::string err;
+
+  // rounding of a long-double metric term to T, optionally moved by one unit in the last place
+  T round_geo(long double v, uint64_t key) const {
+    T r = T(v);
+    if (!jitter) return r;
+    uint64_t h = (key + jitter) * 0x9e3779b97f4a7c15ull;
+    h ^= h >> 31;
+    h *= 0xbf58476d1ce4e5b9ull;
+    h ^= h >> 29;
+    const int k = int(h % 3);
+    if (k == 1) r = std::nextafter(r, std::numeric_limits<T>::infinity());
+    if (k == 2) r = std::nextafter(r, -std::numeric_limits<T>::infinity());
+    return r;
+  }
 
   int setup(int p_, int64_t E_, const int64_t *ev, int q, const double *nodes, const Gas<T> &g,
             T eta_, int flux_, int mform, int64_t nact, const int64_t *act, int nth) {
@@ -601,6 +618,13 @@ struct Oracle : Iface {
         apply_tensor<G>(Iqg, Iqg, Iqg, in.data(), &Xg[c * ng * ng * ng]);
       }
       const int NG = ng * ng * ng;
+      // element-local coordinates: every metric quantity below is a derivative of X, so the
+      // shift by the first node changes nothing but the round-off (which otherwise grows with |X|)
+      G xorig[3];
+      for (int c = 0; c < 3; ++c) {
+        xorig[c] = Xg[c * NG];
+        for (int g2 = 0; g2 < NG; ++g2) Xg[c * NG + g2] -= xorig[c];
+      }
       // dX[c][k] at GLL nodes
       vector<G> dXg(9 * NG);
       for (int c = 0; c < 3; ++c)
@@ -611,7 +635,7 @@ struct Oracle : Iface {
       vector<G> Jm(9 * Ns), xs_g(Ns), detG(Ns);
       for (int c = 0; c < 3; ++c) {
         apply_tensor<G>(Igs, Igs, Igs, &Xg[c * NG], xs_g.data());
-        for (int s = 0; s < Ns; ++s) Xs[(sl * 3 + c) * Ns + s] = T(xs_g[s]);
+        for (int s = 0; s < Ns; ++s) Xs[(sl * 3 + c) * Ns + s] = T(xs_g[s] + xorig[c]);
         for (int k = 0; k < 3; ++k)
           apply_tensor<G>(k == 0 ? Dgs : Igs, k == 1 ? Dgs : Igs, k == 2 ? Dgs : Igs, &Xg[c * NG],
                           &Jm[(c * 3 + k) * Ns]);
@@ -624,7 +648,7 @@ struct Oracle : Iface {
                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
         detG[s] = det;
-        detJ[sl * Ns + s] = T(det);
+        detJ[sl * Ns + s] = round_geo(det, (uint64_t)(e * Ns + s) * 16 + 9);
         if (!(det > 0)) {
 #pragma omp critical
           { bad = 1; bad_e = e; }
@@ -635,6 +659,7 @@ struct Oracle : Iface {
       auto metrics_at = [&](const Mat<G> *Mi[3], const Mat<G> *Md[3], int NT, G *out /*[NT][3][3]*/) {
         if (metric_form == 0) {
           // conservative curl form: Ja^n_i = -[curl_xi I(X_l grad_xi X_m)]_n, (i,m,l) cyclic
+          // (X is element-local here; the curl of a constant times a gradient vanishes)
           vector<G> V(3 * NG);
           for (int i = 0; i < 3; ++i) {
             int m = (i + 1) % 3, l = (i + 2) % 3;
@@ -677,7 +702,7 @@ struct Oracle : Iface {
         const Mat<G> *Mi[3] = {&Igs, &Igs, &Igs}, *Md[3] = {&Dgs, &Dgs, &Dgs};
         vector<G> Jas(Ns * 9);
         metrics_at(Mi, Md, Ns, Jas.data());
-        for (int t = 0; t < Ns * 9; ++t) Ja[sl * Ns * 9 + t] = T(Jas[t]);
+        for (int t = 0; t < Ns * 9; ++t) Ja[sl * Ns * 9 + t] = round_geo(Jas[t], (uint64_t)(e * Ns * 9 + t) * 16 + 1);
       }
       for (int f = 0; f < 6; ++f) {
         int d = f / 2, s = f % 2;
@@ -688,14 +713,16 @@ struct Oracle : Iface {
         metrics_at(Mi, Md, Nfp, Jaf.data());
         G sg = s ? G(1) : G(-1);
         for (int k = 0; k < Nfp; ++k)
-          for (int i = 0; i < 3; ++i) Nf[((sl * 6 + f) * Nfp + k) * 3 + i] = T(sg * Jaf[k * 9 + d * 3 + i]);
+          for (int i = 0; i < 3; ++i)
+            Nf[((sl * 6 + f) * Nfp + k) * 3 + i] =
+                round_geo(sg * Jaf[k * 9 + d * 3 + i], (uint64_t)(((e * 6 + f) * Nfp + k) * 3 + i) * 16 + 2);
         // |J| at face points: interpolation of the solution-point |J| along the normal line
         const vector<G> &ell = s ? BG.lp : BG.lm;
         for (int b = 0; b < n; ++b)
           for (int a = 0; a < n; ++a) {
             G v = 0;
             for (int c = 0; c < n; ++c) v += ell[c] * detG[pt(d, c, a, b)];
-            Jf[(sl * 6 + f) * Nfp + a + n * b] = T(v);
+            Jf[(sl * 6 + f) * Nfp + a + n * b] = round_geo(v, (uint64_t)((e * 6 + f) * Nfp + a + n * b) * 16 + 3);
           }
       }
     }
@@ -966,7 +993,7 @@ const char *ora_last_error() { return g_err.c_str(); }
 
 void *ora_create(int prec, int p, int64_t n_elem, const int64_t *elem_vert, int q, const double *elem_nodes,
                  double gamma, double prandtl, double mu, double eta, int flux, int metric_form,
-                 int64_t n_active, const int64_t *active, int nthreads) {
+                 int64_t n_active, const int64_t *active, int nthreads, uint64_t metric_jitter) {
   if (p < 0 || p > 15) { g_err = "p out of range"; return nullptr; }
   if (nthreads <= 0) {
 #ifdef _OPENMP
@@ -981,6 +1008,7 @@ void *ora_create(int prec, int p, int64_t n_elem, const int64_t *elem_vert, int 
   auto go = [&](auto *o, auto tag) {
     using T = decltype(tag);
     Gas<T> g{T(gamma), T(prandtl), T(mu)};
+    o->jitter = metric_jitter;
     rc = o->setup(p, n_elem, elem_vert, q, elem_nodes, g, T(eta), flux, metric_form, n_active, active, nthreads);
     e = o->err;
     h = o;

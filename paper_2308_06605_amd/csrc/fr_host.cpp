@@ -413,12 +413,20 @@ static void element_geometry(const Basis &B, const GeoOps &O, int q, const doubl
     for (int m = 0; m < nq * nq * nq; ++m) src[m] = (LD)nodes[((size_t)e * nq * nq * nq + m) * 3 + c];
     contract3(up, up, up, src.data(), &X[c * NG]);
   }
+  // element-local coordinates (shifted by the first node): only derivatives of X enter the
+  // metric terms, and without the shift their round-off would grow with |X| / h
+  LD xorig[3];
+  for (int c = 0; c < 3; ++c) {
+    xorig[c] = X[c * NG];
+    for (int g = 0; g < NG; ++g) X[c * NG + g] -= xorig[c];
+  }
   // grad X at the GLL nodes: dX[(c*3+k)*NG]
   std::vector<LD> dX(9 * NG);
   for (int c = 0; c < 3; ++c)
     for (int k = 0; k < 3; ++k)
       contract3(k == 0 ? Dg : Ig, k == 1 ? Dg : Ig, k == 2 ? Dg : Ig, &X[c * NG], &dX[(c * 3 + k) * NG]);
-  // W[i][k] = X_l d_k X_m at the nodes, (i, m, l) cyclic
+  // W[i][k] = X_l d_k X_m at the nodes, (i, m, l) cyclic (local X: the curl of a constant
+  // times a gradient is zero, so the shift leaves the metric unchanged)
   std::vector<LD> W(9 * NG);
   for (int i = 0; i < 3; ++i) {
     int m = (i + 1) % 3, l = (i + 2) % 3;
@@ -449,7 +457,7 @@ static void element_geometry(const Basis &B, const GeoOps &O, int q, const doubl
   std::vector<LD> xs(Ns), J(9 * Ns);
   for (int c = 0; c < 3; ++c) {
     contract3(Is, Is, Is, &X[c * NG], xs.data());
-    for (int s = 0; s < Ns; ++s) G.xyz[((size_t)e * 3 + c) * Ns + s] = (double)xs[s];
+    for (int s = 0; s < Ns; ++s) G.xyz[((size_t)e * 3 + c) * Ns + s] = (double)(xs[s] + xorig[c]);
     for (int k = 0; k < 3; ++k)
       contract3(k == 0 ? Ds : Is, k == 1 ? Ds : Is, k == 2 ? Ds : Is, &X[c * NG], &J[(c * 3 + k) * Ns]);
   }
@@ -497,6 +505,21 @@ static void element_geometry(const Basis &B, const GeoOps &O, int q, const doubl
 // ==========================================================================================
 namespace frk {
 
+Ops1D basis_ops(int p) {
+  frh::Basis B = frh::make_basis(p);
+  Ops1D o;
+  std::memset(&o, 0, sizeof o);
+  const int n = p + 1;
+  for (int i = 0; i < n * n; ++i) o.D[i] = (double)B.D[i];
+  for (int i = 0; i < n; ++i) {
+    o.lm[i] = (double)B.lm[i];
+    o.lp[i] = (double)B.lp[i];
+    o.gcL[i] = (double)B.gcL[i];
+    o.gcR[i] = (double)B.gcR[i];
+  }
+  return o;
+}
+
 std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const double *nodes, double eta,
                             HostMesh &H) {
   using frh::LD;
@@ -505,14 +528,7 @@ std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const do
   H.E = E;
   const int n = p + 1, Ns = n * n * n, Nfp = n * n;
   frh::Basis B = frh::make_basis(p);
-  std::memset(&H.ops, 0, sizeof H.ops);
-  for (int i = 0; i < n * n; ++i) H.ops.D[i] = (double)B.D[i];
-  for (int i = 0; i < n; ++i) {
-    H.ops.lm[i] = (double)B.lm[i];
-    H.ops.lp[i] = (double)B.lp[i];
-    H.ops.gcL[i] = (double)B.gcL[i];
-    H.ops.gcR[i] = (double)B.gcR[i];
-  }
+  H.ops = basis_ops(p);
   frh::Topology T;
   std::string err = frh::pair_faces(E, ev, p, T);
   if (!err.empty()) return err;

@@ -123,6 +123,9 @@ struct HostMesh {
   std::vector<double> xyz;     // [E][3][Ns]
 };
 
+// 1-D operator tables of degree p (computed in long double, rounded to double).
+Ops1D basis_ops(int p);
+
 // Returns "" on success or a message naming the offending element / face.
 std::string build_host_mesh(int p, int q, int64_t E, const int64_t *elem_vert, const double *elem_nodes,
                             double br2_eta, HostMesh &H);

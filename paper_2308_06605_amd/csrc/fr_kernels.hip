@@ -801,6 +801,20 @@ int fr_mesh_geometry_host(const fr_mesh_desc *d, double *geo, double *fgeo, int3
   return FR_OK;
 }
 
+int fr_basis_host(int p, double *D, double *lm, double *lp, double *gcL, double *gcR) {
+  if (p < 0 || p > kMaxP || !D || !lm || !lp || !gcL || !gcR) return fail(FR_ERR_ARG, "bad p or NULL pointer");
+  Ops1D o = basis_ops(p);
+  const int n = p + 1;
+  for (int i = 0; i < n * n; ++i) D[i] = o.D[i];
+  for (int i = 0; i < n; ++i) {
+    lm[i] = o.lm[i];
+    lp[i] = o.lp[i];
+    gcL[i] = o.gcL[i];
+    gcR[i] = o.gcR[i];
+  }
+  return FR_OK;
+}
+
 int fr_mesh_destroy(fr_mesh_t m) {
   if (!m) return FR_OK;
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");

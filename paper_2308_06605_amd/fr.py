@@ -64,9 +64,10 @@ def load():
     L.fr_mesh_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
     L.fr_profile_stages.argtypes = [P, f64, i32, i32, P]
     L.fr_mesh_geometry_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, P, P, P, P]
+    L.fr_basis_host.argtypes = [i32, P, P, P, P, P]
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
-                 "fr_mesh_geometry_host"):
+                 "fr_mesh_geometry_host", "fr_basis_host"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -106,6 +107,14 @@ def geometry_host(mesh, p: int, eta: float = 6.0):
     _check(load().fr_mesh_geometry_host(ctypes.byref(d), geo.ctypes.data, fgeo.ctypes.data,
                                         ftab.ctypes.data, conn.ctypes.data, xyz.ctypes.data))
     return geo, fgeo, ftab, conn, xyz
+
+
+def basis_host(p: int) -> dict:
+    """The library's 1-D operator tables of degree p (fr_basis_host)."""
+    n = p + 1
+    out = {"D": np.empty((n, n)), "lm": np.empty(n), "lp": np.empty(n), "gcL": np.empty(n), "gcR": np.empty(n)}
+    _check(load().fr_basis_host(int(p), *(out[k].ctypes.data for k in ("D", "lm", "lp", "gcL", "gcR"))))
+    return out
 
 
 class FRMesh:
