@@ -43,12 +43,18 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
     n = p + 1
     Ns, Nfp = n ** 3, n * n
     Nf = 6 * Nfp
-    w = 8 if prec == "fp64" else 4
     nv = 20 if viscous else 5
-    k1 = 8 * 5 * Ns + w * (10 * Ns + nv * Nf)
-    k2 = w * 3 * Nfp * (2 * nv + 4 + 10)
-    k3 = 8 * 15 * Ns + w * (10 * Ns + 10 * Nf)
-    stage_min = 8 * 25 * Ns + w * (20 * Ns + 44 * Nf)
+    if prec == "fp64":
+        k1 = 8 * 5 * Ns + 8 * (10 * Ns + nv * Nf)
+        k2 = 8 * 3 * Nfp * (2 * nv + 4 + 10)
+        k3 = 8 * 15 * Ns + 8 * (10 * Ns + 10 * Nf)
+    else:
+        # FP32 form: FP32 geometry copy for the pre-pass, face data as 20 floats + 3 doubles,
+        # face results as 9 floats + 1 double; the volume kernel reads FP64 geometry (mass)
+        k1 = 8 * 5 * Ns + 4 * 10 * Ns + (4 * nv + 8 * 3) * Nf
+        k2 = 3 * Nfp * (2 * (4 * nv + 8 * 3) + 8 * 4 + 4 * 9 + 8)
+        k3 = 8 * 15 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
+    stage_min = 8 * (45 * Ns + 44 * Nf)
     return {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
 
 
@@ -103,6 +109,8 @@ def main():
     ap.add_argument("--flux", default="roe")
     ap.add_argument("--scheme", default="lsrk45")
     ap.add_argument("--dt", type=float, default=2.5e-4)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"],
+                    help="fp32: FP32 operators and fluxes with FP64 state and mass equation")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer once (a known-size "
@@ -121,7 +129,8 @@ def main():
     mu = 1.0 / 1600.0
     mesh = make_workload(args.n, args.p, not args.affine)
     t0 = time.perf_counter()
-    g = fr.FRMesh(mesh, args.p, mu=mu, flux=args.flux)
+    p0 = 1.0 / (1.4 * 0.1 * 0.1)  # TGV reference pressure at Mach 0.1
+    g = fr.FRMesh(mesh, args.p, mu=mu, flux=args.flux, prec=args.prec, ref_rho=1.0, ref_p=p0)
     t_setup = time.perf_counter() - t0
     X = g.sol_coords()
     U = inputs.state_from_coords(X, inputs.tgv_state)
@@ -148,7 +157,7 @@ def main():
 
     # per-kernel mean launch durations (HIP events on the launch stream)
     kms = dict(zip(("prepass", "face", "volume"), g.profile_stages(args.dt, args.scheme, 2)))
-    ab = algorithmic_bytes(args.p)
+    ab = algorithmic_bytes(args.p, args.prec)
     gbs = {k: ab[k] * mesh.n_elem / (kms[k] * 1e-3) / 1e9 for k in kms}
     dominant = max(kms, key=kms.get)
     achieved = gbs[dominant]
@@ -164,7 +173,8 @@ def main():
             cpu = {"error": str(exc)}
 
     wl = (f"TGV Ma0.1 Re1600, {'curved' if not args.affine else 'affine'} periodic {args.n}^3 hex, "
-          f"p={args.p}, {args.flux.capitalize()}+BR2, {args.scheme.upper()} dt={args.dt}")
+          f"p={args.p}, {args.flux.capitalize()}+BR2, {args.scheme.upper()} dt={args.dt}, "
+          f"{'FP64' if args.prec == 'fp64' else 'FP32 operators/fluxes, FP64 state and mass'}")
     out = {
         "metric": "DOF-updates/s per RK stage",
         "value": value,
@@ -176,7 +186,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl, "n_elem": mesh.n_elem, "dof": dof, "p": args.p,
                    "stages_per_step": stages, "parallelism": "single GPU"},

@@ -46,7 +46,9 @@ enum fr_status {
 };
 
 enum fr_flux { FR_RUSANOV = 0, FR_ROE = 1 };     /* interface Riemann solver */
-enum fr_prec { FR_FP64 = 0, FR_FP32 = 1 };       /* FP32: operators and fluxes in FP32, state FP64 */
+enum fr_prec { FR_FP64 = 0, FR_FP32 = 1 };       /* FP32: operators and fluxes in FP32 with a
+                                                    reference-state split; state, RK registers
+                                                    and the mass equation in FP64 */
 enum fr_scheme { FR_RK4 = 0, FR_LSRK45 = 1 };    /* classical RK4; Carpenter-Kennedy 5-stage 2N */
 
 /* Mesh and physics description, read by fr_mesh_create (section "FR Algorithm", Eq. (1)).
@@ -63,7 +65,12 @@ enum fr_scheme { FR_RK4 = 0, FR_LSRK45 = 1 };    /* classical RK4; Carpenter-Ken
  *   mu         dynamic viscosity (constant); mu == 0 gives the Euler equations.
  *   br2_eta    BR2 penalty factor (the number of faces, 6, is the usual choice).
  *   flux       enum fr_flux.   prec: enum fr_prec.
- *   check_finite  non-zero: fr_residual scans its result and reports FR_ERR_NONFINITE. */
+ *   check_finite  non-zero: fr_residual scans its result and reports FR_ERR_NONFINITE.
+ *   ref_rho, ref_p  reference state at rest used by FR_FP32 (ignored by FR_FP64): the FP32
+ *              operators work on U - U_ref, formed in double precision, with the reference
+ *              pressure and enthalpy split out of the momentum and energy fluxes. Choose the
+ *              flow's mean density and pressure (for the Taylor-Green vortex at Mach 0.1:
+ *              1 and 1/(gamma 0.01)). ref_rho must be > 0 for FR_FP32. */
 typedef struct {
   int32_t p;
   int32_t q;
@@ -78,6 +85,8 @@ typedef struct {
   int32_t prec;
   int32_t check_finite;
   int32_t reserved; /* must be 0 */
+  double ref_rho;
+  double ref_p;
 } fr_mesh_desc;
 
 /* Build a mesh on the current HIP device: pair faces (sort-and-match on corner ids, as the
@@ -111,6 +120,13 @@ int fr_residual(fr_mesh_t m, double *R, int on_device);
  * point) and the volume kernel (corrected gradient, flux divergence and correction, and the
  * RK register update). Enqueued on the stream; returns without waiting. */
 int fr_rk_step(fr_mesh_t m, double dt, int scheme, int n_steps);
+
+/* Kinetic-energy diagnostics of the current state (a quadrature over the mesh with the
+ * solution-point weights w and |J|): out[0] = E_k = sum w|J| |m|^2/(2 rho) / sum w|J|,
+ * out[1] = dE_k/dt = sum w|J| (u . R_m - |u|^2 R_rho / 2) / sum w|J| evaluated from the
+ * residual R of the handle's precision (one residual is computed). The dissipation rate is
+ * -out[1]. The reduction is deterministic (fixed order). Waits for the stream. */
+int fr_kinetic_energy(fr_mesh_t m, double *out);
 
 /* Sizes of the handle: n_elem, points per element, bytes of device memory held. */
 int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_bytes);

@@ -1,0 +1,171 @@
+// fr_device.h -- device-side building blocks shared by the FP64 and FP32 kernels of libfr:
+// the physical and numerical fluxes of the compressible Navier-Stokes equations (the paper's
+// section "FR Algorithm", Eq. (1) and the interface Riemann solver), the launch configuration
+// per polynomial degree and the 1-D operator tables passed to the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fr_internal.h"
+
+using namespace frk;
+
+// ------------------------------------------------------------------------------------------
+// Device physics (Eq. (1)): inviscid flux, viscous flux with constant mu, Riemann solvers.
+// ------------------------------------------------------------------------------------------
+template <typename real>
+struct Phys {
+  real gamma, gm1, mu, kappa;
+};
+
+template <typename real>
+__device__ __forceinline__ real pressure(const real U[5], real gm1) {
+  const real ir = real(1) / U[0];
+  return gm1 * (U[4] - real(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir);
+}
+
+// Inviscid flux along a unit or scaled direction n: F(U).n, plus u.n and c.
+template <typename real>
+__device__ __forceinline__ void flux_n(const real U[5], const real n[3], const Phys<real> &ph, real F[5],
+                                       real &un, real &c) {
+  const real ir = real(1) / U[0];
+  const real u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
+  const real p = ph.gm1 * (U[4] - real(0.5) * U[0] * (u * u + v * v + w * w));
+  un = u * n[0] + v * n[1] + w * n[2];
+  F[0] = U[0] * un;
+  F[1] = U[1] * un + p * n[0];
+  F[2] = U[2] * un + p * n[1];
+  F[3] = U[3] * un + p * n[2];
+  F[4] = (U[4] + p) * un;
+  c = sqrt(ph.gamma * p * ir);
+}
+
+template <typename real>
+__device__ __forceinline__ void rusanov(const real UL[5], const real UR[5], const real n[3], const Phys<real> &ph,
+                                        real F[5]) {
+  real FL[5], FR[5], unL, unR, cL, cR;
+  flux_n(UL, n, ph, FL, unL, cL);
+  flux_n(UR, n, ph, FR, unR, cR);
+  const real lam = fmax(fabs(unL) + cL, fabs(unR) + cR);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lam * (UR[v] - UL[v]);
+}
+
+// Roe: mean flux minus half of sum |lambda_k| alpha_k r_k; sqrt(rho) averages; no entropy fix.
+template <typename real>
+__device__ __forceinline__ void roe(const real UL[5], const real UR[5], const real n[3], const Phys<real> &ph,
+                                    real F[5]) {
+  real FL[5], FR[5], t0, t1;
+  flux_n(UL, n, ph, FL, t0, t1);
+  flux_n(UR, n, ph, FR, t0, t1);
+  const real rL = UL[0], rR = UR[0];
+  const real iL = real(1) / rL, iR = real(1) / rR;
+  const real uL[3] = {UL[1] * iL, UL[2] * iL, UL[3] * iL};
+  const real uR[3] = {UR[1] * iR, UR[2] * iR, UR[3] * iR};
+  const real pL = ph.gm1 * (UL[4] - real(0.5) * rL * (uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]));
+  const real pR = ph.gm1 * (UR[4] - real(0.5) * rR * (uR[0] * uR[0] + uR[1] * uR[1] + uR[2] * uR[2]));
+  const real HL = (UL[4] + pL) * iL, HR = (UR[4] + pR) * iR;
+  const real sL = sqrt(rL), sR = sqrt(rR);
+  const real is = real(1) / (sL + sR);
+  const real rt = sL * sR;
+  real ut[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ut[i] = (sL * uL[i] + sR * uR[i]) * is;
+  const real Ht = (sL * HL + sR * HR) * is;
+  const real q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const real c2 = ph.gm1 * (Ht - real(0.5) * q2);
+  const real ct = sqrt(c2);
+  const real ic2 = real(1) / c2;
+  const real unt = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+  const real dr = rR - rL, dp = pR - pL;
+  const real du[3] = {uR[0] - uL[0], uR[1] - uL[1], uR[2] - uL[2]};
+  const real dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const real a1 = real(0.5) * (dp - rt * ct * dun) * ic2;
+  const real a5 = real(0.5) * (dp + rt * ct * dun) * ic2;
+  const real a2 = dr - dp * ic2;
+  const real l1 = fabs(unt - ct), l2 = fabs(unt), l5 = fabs(unt + ct);
+  const real w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2;
+  real dis[5];
+  dis[0] = w1 + w5 + w2;
+  real udu = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const real sh = du[i] - dun * n[i];
+    dis[1 + i] = w1 * (ut[i] - ct * n[i]) + w5 * (ut[i] + ct * n[i]) + w2 * ut[i] + l2 * rt * sh;
+    udu += ut[i] * sh;
+  }
+  dis[4] = w1 * (Ht - unt * ct) + w5 * (Ht + unt * ct) + w2 * real(0.5) * q2 + l2 * rt * udu;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * dis[v];
+}
+
+// Viscous flux Fv[i][v] from U and the gradient of the conserved variables G[i][v].
+template <typename real>
+__device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], const Phys<real> &ph, real Fv[3][5]) {
+  const real ir = real(1) / U[0];
+  const real u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
+  const real e = U[4] * ir;
+  real du[3][3], dT[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) du[i][j] = (G[i][1 + j] - u[j] * G[i][0]) * ir;
+    const real de = (G[i][4] - e * G[i][0]) * ir;
+    dT[i] = ph.gm1 * (de - (u[0] * du[i][0] + u[1] * du[i][1] + u[2] * du[i][2]));
+  }
+  const real lam = real(-2.0 / 3.0) * ph.mu * (du[0][0] + du[1][1] + du[2][2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    real tau[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tau[j] = ph.mu * (du[j][i] + du[i][j]) + (i == j ? lam : real(0));
+    Fv[i][0] = 0;
+    Fv[i][1] = tau[0];
+    Fv[i][2] = tau[1];
+    Fv[i][3] = tau[2];
+    Fv[i][4] = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + ph.kappa * dT[i];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Kernel configuration
+// ------------------------------------------------------------------------------------------
+template <int P>
+struct Cfg {
+  static constexpr int N = P + 1;
+  static constexpr int NS = N * N * N;
+  static constexpr int NFP = N * N;
+  static constexpr int NF = 6 * NFP;
+  static constexpr int EPB = (256 / NS) > 64 ? 64 : ((256 / NS) > 0 ? (256 / NS) : 1);  // elements per block
+  static constexpr int BLOCK = EPB * NS;
+};
+
+// Occupancy targets (waves per SIMD) per kernel and degree; 0 lets the compiler decide. Forcing
+// more waves than the compiler picks spilled to scratch (HBM traffic) in every measured case.
+#ifndef FR_WPE_PREPASS
+#define FR_WPE_PREPASS(P) 0
+#endif
+#ifndef FR_WPE_FACE
+#define FR_WPE_FACE(P) 0
+#endif
+#ifndef FR_WPE_VOLUME
+#define FR_WPE_VOLUME(P) 0
+#endif
+#define FR_WPE_ATTR(w) __attribute__((amdgpu_waves_per_eu((w) > 0 ? (w) : 1, (w) > 0 ? 8 : 8)))
+
+template <typename real>
+struct OpsT {
+  real D[kMaxN * kMaxN];
+  real lm[kMaxN];
+  real lp[kMaxN];
+  real gcL[kMaxN];
+  real gcR[kMaxN];
+};
+
+// index of solution point with coordinate c along direction d and (a, b) along the face's
+// tangential directions (increasing axis order)
+template <int N>
+__device__ __forceinline__ int line_pt(int d, int c, int a, int b) {
+  return d == 0 ? c + N * (a + N * b) : (d == 1 ? a + N * (c + N * b) : a + N * (b + N * c));
+}
+

@@ -104,6 +104,14 @@ struct DeviceMesh {
   FaceRef *fref = nullptr;   // [E][6]
   void *face = nullptr;   // [E][6][20][Nfp]: U_f (5) then broken gradient G[i][v] (15, i-major)
   void *fout = nullptr;   // [F][10][Nfp]: J = (U_R - U_L)/2 (5), owner's F^{I,perp} (5)
+  // FP32 form (prec == 1): FP32 copies of the volume geometry and of the face data; the
+  // momentum at face points and the mass fluxes stay FP64
+  void *geo32 = nullptr;    // [E][10][Ns] float
+  void *face32 = nullptr;   // [E][6][20][Nfp] float: U - U_ref (5), broken gradient (15)
+  void *facem = nullptr;    // [E][6][3][Nfp] double: momentum at the face points
+  void *fout32 = nullptr;   // [F][9][Nfp] float: J (5), owner's momentum flux (3), reduced energy flux
+  void *foutm = nullptr;    // [F][Nfp] double: owner's mass flux
+  double ref_rho = 1.0, ref_p = 0.0;
   int *flag = nullptr;    // non-finite flag
   bool check_finite = false;
   void *stream = nullptr;
@@ -122,6 +130,11 @@ struct HostMesh {
   std::vector<FaceRef> fref;   // [E][6]
   std::vector<double> xyz;     // [E][3][Ns]
 };
+
+// Enqueue one RK stage (or a residual) of the FP32 form (fr_kernels32.hip); 0 or a negative
+// FR_ERR_* code with `err` set. ms (optional) accumulates the three kernel durations.
+int launch_stage32(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
+                   std::string &err);
 
 // 1-D operator tables of degree p (computed in long double, rounded to double).
 Ops1D basis_ops(int p);

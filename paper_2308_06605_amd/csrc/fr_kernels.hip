@@ -27,168 +27,10 @@
 #include <vector>
 
 #include "fr.h"
+#include "fr_device.h"
 #include "fr_internal.h"
 
 using namespace frk;
-
-// ------------------------------------------------------------------------------------------
-// Device physics (Eq. (1)): inviscid flux, viscous flux with constant mu, Riemann solvers.
-// ------------------------------------------------------------------------------------------
-template <typename real>
-struct Phys {
-  real gamma, gm1, mu, kappa;
-};
-
-template <typename real>
-__device__ __forceinline__ real pressure(const real U[5], real gm1) {
-  const real ir = real(1) / U[0];
-  return gm1 * (U[4] - real(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * ir);
-}
-
-// Inviscid flux along a unit or scaled direction n: F(U).n, plus u.n and c.
-template <typename real>
-__device__ __forceinline__ void flux_n(const real U[5], const real n[3], const Phys<real> &ph, real F[5],
-                                       real &un, real &c) {
-  const real ir = real(1) / U[0];
-  const real u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
-  const real p = ph.gm1 * (U[4] - real(0.5) * U[0] * (u * u + v * v + w * w));
-  un = u * n[0] + v * n[1] + w * n[2];
-  F[0] = U[0] * un;
-  F[1] = U[1] * un + p * n[0];
-  F[2] = U[2] * un + p * n[1];
-  F[3] = U[3] * un + p * n[2];
-  F[4] = (U[4] + p) * un;
-  c = sqrt(ph.gamma * p * ir);
-}
-
-template <typename real>
-__device__ __forceinline__ void rusanov(const real UL[5], const real UR[5], const real n[3], const Phys<real> &ph,
-                                        real F[5]) {
-  real FL[5], FR[5], unL, unR, cL, cR;
-  flux_n(UL, n, ph, FL, unL, cL);
-  flux_n(UR, n, ph, FR, unR, cR);
-  const real lam = fmax(fabs(unL) + cL, fabs(unR) + cR);
-#pragma unroll
-  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lam * (UR[v] - UL[v]);
-}
-
-// Roe: mean flux minus half of sum |lambda_k| alpha_k r_k; sqrt(rho) averages; no entropy fix.
-template <typename real>
-__device__ __forceinline__ void roe(const real UL[5], const real UR[5], const real n[3], const Phys<real> &ph,
-                                    real F[5]) {
-  real FL[5], FR[5], t0, t1;
-  flux_n(UL, n, ph, FL, t0, t1);
-  flux_n(UR, n, ph, FR, t0, t1);
-  const real rL = UL[0], rR = UR[0];
-  const real iL = real(1) / rL, iR = real(1) / rR;
-  const real uL[3] = {UL[1] * iL, UL[2] * iL, UL[3] * iL};
-  const real uR[3] = {UR[1] * iR, UR[2] * iR, UR[3] * iR};
-  const real pL = ph.gm1 * (UL[4] - real(0.5) * rL * (uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]));
-  const real pR = ph.gm1 * (UR[4] - real(0.5) * rR * (uR[0] * uR[0] + uR[1] * uR[1] + uR[2] * uR[2]));
-  const real HL = (UL[4] + pL) * iL, HR = (UR[4] + pR) * iR;
-  const real sL = sqrt(rL), sR = sqrt(rR);
-  const real is = real(1) / (sL + sR);
-  const real rt = sL * sR;
-  real ut[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) ut[i] = (sL * uL[i] + sR * uR[i]) * is;
-  const real Ht = (sL * HL + sR * HR) * is;
-  const real q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
-  const real c2 = ph.gm1 * (Ht - real(0.5) * q2);
-  const real ct = sqrt(c2);
-  const real ic2 = real(1) / c2;
-  const real unt = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
-  const real dr = rR - rL, dp = pR - pL;
-  const real du[3] = {uR[0] - uL[0], uR[1] - uL[1], uR[2] - uL[2]};
-  const real dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
-  const real a1 = real(0.5) * (dp - rt * ct * dun) * ic2;
-  const real a5 = real(0.5) * (dp + rt * ct * dun) * ic2;
-  const real a2 = dr - dp * ic2;
-  const real l1 = fabs(unt - ct), l2 = fabs(unt), l5 = fabs(unt + ct);
-  const real w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2;
-  real dis[5];
-  dis[0] = w1 + w5 + w2;
-  real udu = 0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const real sh = du[i] - dun * n[i];
-    dis[1 + i] = w1 * (ut[i] - ct * n[i]) + w5 * (ut[i] + ct * n[i]) + w2 * ut[i] + l2 * rt * sh;
-    udu += ut[i] * sh;
-  }
-  dis[4] = w1 * (Ht - unt * ct) + w5 * (Ht + unt * ct) + w2 * real(0.5) * q2 + l2 * rt * udu;
-#pragma unroll
-  for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * dis[v];
-}
-
-// Viscous flux Fv[i][v] from U and the gradient of the conserved variables G[i][v].
-template <typename real>
-__device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], const Phys<real> &ph, real Fv[3][5]) {
-  const real ir = real(1) / U[0];
-  const real u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
-  const real e = U[4] * ir;
-  real du[3][3], dT[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) du[i][j] = (G[i][1 + j] - u[j] * G[i][0]) * ir;
-    const real de = (G[i][4] - e * G[i][0]) * ir;
-    dT[i] = ph.gm1 * (de - (u[0] * du[i][0] + u[1] * du[i][1] + u[2] * du[i][2]));
-  }
-  const real lam = real(-2.0 / 3.0) * ph.mu * (du[0][0] + du[1][1] + du[2][2]);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    real tau[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) tau[j] = ph.mu * (du[j][i] + du[i][j]) + (i == j ? lam : real(0));
-    Fv[i][0] = 0;
-    Fv[i][1] = tau[0];
-    Fv[i][2] = tau[1];
-    Fv[i][3] = tau[2];
-    Fv[i][4] = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + ph.kappa * dT[i];
-  }
-}
-
-// ------------------------------------------------------------------------------------------
-// Kernel configuration
-// ------------------------------------------------------------------------------------------
-template <int P>
-struct Cfg {
-  static constexpr int N = P + 1;
-  static constexpr int NS = N * N * N;
-  static constexpr int NFP = N * N;
-  static constexpr int NF = 6 * NFP;
-  static constexpr int EPB = (256 / NS) > 64 ? 64 : ((256 / NS) > 0 ? (256 / NS) : 1);  // elements per block
-  static constexpr int BLOCK = EPB * NS;
-};
-
-// Occupancy targets (waves per SIMD) per kernel and degree; 0 lets the compiler decide. Forcing
-// more waves than the compiler picks spilled to scratch (HBM traffic) in every measured case.
-#ifndef FR_WPE_PREPASS
-#define FR_WPE_PREPASS(P) 0
-#endif
-#ifndef FR_WPE_FACE
-#define FR_WPE_FACE(P) 0
-#endif
-#ifndef FR_WPE_VOLUME
-#define FR_WPE_VOLUME(P) 0
-#endif
-#define FR_WPE_ATTR(w) __attribute__((amdgpu_waves_per_eu((w) > 0 ? (w) : 1, (w) > 0 ? 8 : 8)))
-
-template <typename real>
-struct OpsT {
-  real D[kMaxN * kMaxN];
-  real lm[kMaxN];
-  real lp[kMaxN];
-  real gcL[kMaxN];
-  real gcR[kMaxN];
-};
-
-// index of solution point with coordinate c along direction d and (a, b) along the face's
-// tangential directions (increasing axis order)
-template <int N>
-__device__ __forceinline__ int line_pt(int d, int c, int a, int b) {
-  return d == 0 ? c + N * (a + N * b) : (d == 1 ? a + N * (c + N * b) : a + N * (b + N * c));
-}
 
 // ------------------------------------------------------------------------------------------
 // K1: element pre-pass
@@ -542,6 +384,39 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k
   }
 }
 
+// Per-block partial sums of w|J| (1), w|J| |m|^2/(2 rho) (2) and w|J| (u.R_m - |u|^2 R_rho/2)
+// (3); one block per 256 solution points, fixed reduction order.
+__global__ __launch_bounds__(256) void k_kinetic(const double *__restrict__ U, const double *__restrict__ R,
+                                                 const double *__restrict__ geo, int64_t E, int Ns, int n,
+                                                 const double *__restrict__ w1d, double *__restrict__ part) {
+  __shared__ double s[3][256];
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double a = 0, b = 0, c = 0;
+  if (gid < E * Ns) {
+    const int64_t e = gid / Ns;
+    const int t = (int)(gid - e * Ns);
+    const double wJ = w1d[t % n] * w1d[(t / n) % n] * w1d[t / (n * n)] / geo[(e * 10 + 9) * Ns + t];
+    const double *u = U + e * 5 * Ns + t;
+    const double *r = R + e * 5 * Ns + t;
+    const double rho = u[0], m0 = u[Ns], m1 = u[2 * Ns], m2 = u[3 * Ns];
+    const double q2 = (m0 * m0 + m1 * m1 + m2 * m2) / (rho * rho);
+    a = wJ;
+    b = wJ * 0.5 * rho * q2;
+    c = wJ * ((m0 * r[Ns] + m1 * r[2 * Ns] + m2 * r[3 * Ns]) / rho - 0.5 * q2 * r[0]);
+  }
+  s[0][threadIdx.x] = a;
+  s[1][threadIdx.x] = b;
+  s[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+      for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part[blockIdx.x * 3 + q] = s[q][0];
+}
+
 __global__ void k_nonfinite(const double *__restrict__ R, int64_t n, int *flag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -640,7 +515,11 @@ static int launch_stage_p(DeviceMesh &dm, const double *X, StageArgs st, double 
 
 static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
                         double *ms = nullptr) {
-  if (dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "only FR_FP64 is built in this path");
+  if (dm.prec == FR_FP32) {
+    std::string err;
+    int rc = launch_stage32(dm, X, st, o, r1, r2, ms, err);
+    return rc ? fail(rc, err) : FR_OK;
+  }
   return dm.viscous ? launch_stage_p<double, true>(dm, X, st, o, r1, r2, ms)
                     : launch_stage_p<double, false>(dm, X, st, o, r1, r2, ms);
 }
@@ -717,7 +596,8 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   if (!d->elem_vert || !d->elem_nodes) return fail(FR_ERR_ARG, "elem_vert / elem_nodes is NULL");
   if (d->flux != FR_RUSANOV && d->flux != FR_ROE) return fail(FR_ERR_ARG, "unknown flux");
   if (d->prec != FR_FP64 && d->prec != FR_FP32) return fail(FR_ERR_ARG, "unknown precision");
-  if (d->prec == FR_FP32) return fail(FR_ERR_UNSUPPORTED, "FR_FP32 is not built yet");
+  if (d->prec == FR_FP32 && !(d->ref_rho > 0.0 && d->ref_p >= 0.0))
+    return fail(FR_ERR_ARG, "FR_FP32 needs ref_rho > 0 and ref_p >= 0");
   if (!(d->gamma > 1.0) || !(d->prandtl > 0.0) || !(d->mu >= 0.0) || !(d->br2_eta >= 0.0))
     return fail(FR_ERR_ARG, "gamma > 1, prandtl > 0, mu >= 0 and br2_eta >= 0 are required");
   if (d->reserved != 0) return fail(FR_ERR_ARG, "reserved must be 0");
@@ -756,11 +636,23 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   if (!rc) rc = alloc((void **)&dm.U, M * sizeof(double));
   if (!rc) rc = alloc(&dm.geo, H.geo.size() * sizeof(double));
   dm.F = (int64_t)H.ftab.size();
+  dm.ref_rho = d->ref_rho;
+  dm.ref_p = d->ref_p;
   if (!rc) rc = alloc(&dm.fgeo, H.fgeo.size() * sizeof(double));
   if (!rc) rc = alloc((void **)&dm.ftab, H.ftab.size() * sizeof(FaceRec));
   if (!rc) rc = alloc((void **)&dm.fref, H.fref.size() * sizeof(FaceRef));
-  if (!rc) rc = alloc(&dm.face, (size_t)dm.E * 6 * 20 * dm.Nfp * sizeof(double));
-  if (!rc) rc = alloc(&dm.fout, (size_t)dm.F * 10 * dm.Nfp * sizeof(double));
+  std::vector<float> geo32;
+  if (dm.prec == FR_FP64) {
+    if (!rc) rc = alloc(&dm.face, (size_t)dm.E * 6 * 20 * dm.Nfp * sizeof(double));
+    if (!rc) rc = alloc(&dm.fout, (size_t)dm.F * 10 * dm.Nfp * sizeof(double));
+  } else {
+    geo32.assign(H.geo.begin(), H.geo.end());
+    if (!rc) rc = alloc(&dm.geo32, geo32.size() * sizeof(float));
+    if (!rc) rc = alloc(&dm.face32, (size_t)dm.E * 6 * 20 * dm.Nfp * sizeof(float));
+    if (!rc) rc = alloc(&dm.facem, (size_t)dm.E * 6 * 3 * dm.Nfp * sizeof(double));
+    if (!rc) rc = alloc(&dm.fout32, (size_t)dm.F * 9 * dm.Nfp * sizeof(float));
+    if (!rc) rc = alloc(&dm.foutm, (size_t)dm.F * dm.Nfp * sizeof(double));
+  }
   if (!rc) rc = alloc((void **)&dm.flag, sizeof(int));
   if (rc) {
     fr_mesh_destroy(m);
@@ -773,6 +665,8 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   if (e3 == hipSuccess)
     e3 = hipMemcpyAsync(dm.fref, H.fref.data(), H.fref.size() * sizeof(FaceRef), hipMemcpyHostToDevice, s);
   hipError_t e4 = hipMemsetAsync(dm.U, 0, M * sizeof(double), s);
+  if (e4 == hipSuccess && dm.geo32)
+    e4 = hipMemcpyAsync(dm.geo32, geo32.data(), geo32.size() * sizeof(float), hipMemcpyHostToDevice, s);
   hipError_t e5 = hipStreamSynchronize(s);  // host vectors die at return
   if (e1 || e2 || e3 || e4 || e5) {
     fr_mesh_destroy(m);
@@ -821,7 +715,8 @@ int fr_mesh_destroy(fr_mesh_t m) {
   DeviceMesh &dm = m->dm;
   if (dm.stream) (void)hipStreamSynchronize((hipStream_t)dm.stream);
   else (void)hipDeviceSynchronize();
-  void *bufs[] = {dm.U, dm.R1, dm.R2, dm.geo, dm.fgeo, dm.ftab, dm.fref, dm.face, dm.fout, dm.flag};
+  void *bufs[] = {dm.U,     dm.R1,    dm.R2,    dm.geo,    dm.fgeo,  dm.ftab,  dm.fref, dm.face,
+                  dm.fout,  dm.geo32, dm.face32, dm.facem, dm.fout32, dm.foutm, dm.flag};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   m->magic = 0;
@@ -900,6 +795,53 @@ int fr_rk_step(fr_mesh_t m, double dt, int scheme, int n_steps) {
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
   if (n_steps < 0 || !std::isfinite(dt)) return fail(FR_ERR_ARG, "bad dt or n_steps");
   return run_steps(m, dt, scheme, n_steps, nullptr);
+}
+
+int fr_kinetic_energy(fr_mesh_t m, double *out) {
+  if (!valid(m) || !out) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  DeviceMesh &dm = m->dm;
+  const size_t M = (size_t)dm.E * 5 * dm.Ns;
+  const int64_t npts = dm.E * dm.Ns;
+  const int64_t nblk = (npts + 255) / 256;
+  hipStream_t s = (hipStream_t)dm.stream;
+  // Gauss-Legendre weights from the correction tables: w_a = l_a(+1) / g_R'(x_a)
+  double w[kMaxN];
+  for (int a = 0; a < dm.n; ++a) w[a] = dm.ops.lp[a] / dm.ops.gcR[a];
+  double *R = nullptr, *part = nullptr, *wd = nullptr;
+  std::vector<double> hp(nblk * 3);
+  int rc = FR_OK;
+  hipError_t e = hipMalloc(&R, M * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&part, nblk * 3 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&wd, kMaxN * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(wd, w, kMaxN * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) rc = fail(FR_ERR_HIP, std::string("kinetic energy setup: ") + hipGetErrorString(e));
+  if (rc == FR_OK) {
+    StageArgs st{};
+    st.mode = kModeResidual;
+    rc = launch_stage(dm, dm.U, st, R, nullptr, nullptr);
+  }
+  if (rc == FR_OK) {
+    hipLaunchKernelGGL(k_kinetic, dim3((unsigned)nblk), dim3(256), 0, s, dm.U, R, (const double *)dm.geo, dm.E,
+                       dm.Ns, dm.n, wd, part);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, nblk * 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(FR_ERR_HIP, std::string("kinetic energy: ") + hipGetErrorString(e));
+  }
+  if (rc == FR_OK) {
+    double a = 0, b = 0, c = 0;
+    for (int64_t i = 0; i < nblk; ++i) {
+      a += hp[i * 3];
+      b += hp[i * 3 + 1];
+      c += hp[i * 3 + 2];
+    }
+    out[0] = b / a;
+    out[1] = c / a;
+  }
+  if (R) (void)hipFree(R);
+  if (part) (void)hipFree(part);
+  if (wd) (void)hipFree(wd);
+  return rc;
 }
 
 int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_bytes) {

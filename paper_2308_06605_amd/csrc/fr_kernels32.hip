@@ -1,0 +1,600 @@
+// fr_kernels32.hip -- the FP32 form of the FR stage (enum FR_FP32): operators and fluxes in
+// FP32 with FP64 state, RK registers and mass equation.
+//
+// At low Mach number the conserved fluxes are dominated by constants: the pressure p0 in the
+// momentum flux and the enthalpy H ~ c^2/(gamma-1) in the energy flux are 10^3-10^4 times their
+// divergence, and demoting them costs 0.4-2 % of the residual. This form therefore works on
+// U' = U - U_ref (formed in FP64; U_ref = (rho_r, 0, 0, 0, E_r) at rest) and splits fluxes:
+//
+//   mass     F_rho = m                                  FP64 throughout (volume and face)
+//   momentum F_m   = m u + p' I,  p' = p - p_r          FP32 (the constant p_r I has zero
+//                                                       FR divergence and is dropped)
+//   energy   F_E   = H_r m + h' m,  h' = H - H_r        FP32 for h' m; the H_r m part is
+//                                                       H_r times the mass flux, so
+//                                                       R_E = R''_E + H_r R_rho in FP64
+//
+// Each identity is exact in exact arithmetic (the FR operator is linear in the flux and a
+// constant flux has zero residual), so this computes the same residual as the FP64 form up to
+// FP32 round-off in the reduced parts. Common fluxes: the Rusanov / Roe dissipation of the
+// reduced energy E'' = E - H_r rho uses the same wave decomposition as the FP64 solvers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "fr.h"
+#include "fr_device.h"
+#include "fr_internal.h"
+
+namespace {
+
+struct Ref32 {
+  float rho, E, H;    // reference density, energy, enthalpy (FP32 copies)
+  double rho_d, E_d, H_d;
+  float p;            // reference pressure
+};
+
+// Reduced inviscid flux along unit n of U' (rho', m, E'), and the speeds u.n, c.
+//   Fr[0] = m.n (mass, used for the dissipation bookkeeping only)
+//   Fr[1..3] = m u.n + p' n;  Fr[4] = h' m.n
+__device__ __forceinline__ void reduced_flux_n(const float Up[5], const float n[3], const Phys<float> &ph,
+                                               const Ref32 &r, float Fr[5], float &un, float &c, float &pp,
+                                               float &hp) {
+  const float rho = r.rho + Up[0];
+  const float ir = 1.0f / rho;
+  const float u = Up[1] * ir, v = Up[2] * ir, w = Up[3] * ir;
+  pp = ph.gm1 * (Up[4] - 0.5f * rho * (u * u + v * v + w * w));  // p - p_r (u_ref = 0)
+  hp = (Up[4] - r.H * Up[0] + pp) * ir;                            // H - H_r
+  un = u * n[0] + v * n[1] + w * n[2];
+  const float mn = Up[1] * n[0] + Up[2] * n[1] + Up[3] * n[2];
+  Fr[0] = mn;
+  Fr[1] = Up[1] * un + pp * n[0];
+  Fr[2] = Up[2] * un + pp * n[1];
+  Fr[3] = Up[3] * un + pp * n[2];
+  Fr[4] = hp * mn;
+  c = sqrtf(ph.gamma * (r.p + pp) * ir);
+}
+
+// Common reduced flux: Fr[0] carries only the dissipative part of the mass flux (its central
+// part is formed in FP64 by the caller); Fr[1..3] momentum; Fr[4] energy minus H_r times mass.
+__device__ __forceinline__ void riemann32(const float UL[5], const float UR[5], const float n[3],
+                                          const Phys<float> &ph, const Ref32 &r, int flux, float Fr[5]) {
+  float FL[5], FR[5], unL, unR, cL, cR, pL, pR, hL, hR;
+  reduced_flux_n(UL, n, ph, r, FL, unL, cL, pL, hL);
+  reduced_flux_n(UR, n, ph, r, FR, unR, cR, pR, hR);
+  float dis[5];
+  if (flux == 0) {
+    const float lam = fmaxf(fabsf(unL) + cL, fabsf(unR) + cR);
+    dis[0] = lam * (UR[0] - UL[0]);
+    dis[1] = lam * (UR[1] - UL[1]);
+    dis[2] = lam * (UR[2] - UL[2]);
+    dis[3] = lam * (UR[3] - UL[3]);
+    dis[4] = lam * ((UR[4] - UL[4]) - r.H * (UR[0] - UL[0]));
+  } else {
+    const float rL = r.rho + UL[0], rR = r.rho + UR[0];
+    const float iL = 1.0f / rL, iR = 1.0f / rR;
+    const float uL[3] = {UL[1] * iL, UL[2] * iL, UL[3] * iL};
+    const float uR[3] = {UR[1] * iR, UR[2] * iR, UR[3] * iR};
+    const float sL = sqrtf(rL), sR = sqrtf(rR);
+    const float is = 1.0f / (sL + sR);
+    const float rt = sL * sR;
+    float ut[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ut[i] = (sL * uL[i] + sR * uR[i]) * is;
+    const float ht = (sL * hL + sR * hR) * is;  // Roe-averaged H - H_r
+    const float q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    const float c2 = ph.gm1 * ((r.H + ht) - 0.5f * q2);
+    const float ct = sqrtf(c2);
+    const float ic2 = 1.0f / c2;
+    const float unt = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+    const float dr = UR[0] - UL[0], dp = pR - pL;
+    const float du[3] = {uR[0] - uL[0], uR[1] - uL[1], uR[2] - uL[2]};
+    const float dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+    const float a1 = 0.5f * (dp - rt * ct * dun) * ic2;
+    const float a5 = 0.5f * (dp + rt * ct * dun) * ic2;
+    const float a2 = dr - dp * ic2;
+    const float l1 = fabsf(unt - ct), l2 = fabsf(unt), l5 = fabsf(unt + ct);
+    const float w1 = l1 * a1, w5 = l5 * a5, w2 = l2 * a2;
+    dis[0] = w1 + w5 + w2;
+    float udu = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float sh = du[i] - dun * n[i];
+      dis[1 + i] = w1 * (ut[i] - ct * n[i]) + w5 * (ut[i] + ct * n[i]) + w2 * ut[i] + l2 * rt * sh;
+      udu += ut[i] * sh;
+    }
+    // energy eigenvector entries minus H_r times the mass entries
+    dis[4] = w1 * (ht - unt * ct) + w5 * (ht + unt * ct) + w2 * (0.5f * q2 - r.H) + l2 * rt * udu;
+  }
+  Fr[0] = -0.5f * dis[0];
+#pragma unroll
+  for (int v = 1; v < 5; ++v) Fr[v] = 0.5f * (FL[v] + FR[v]) - 0.5f * dis[v];
+}
+
+// full float state from U' (for the viscous flux)
+__device__ __forceinline__ void full_state(const float Up[5], const Ref32 &r, float U[5]) {
+  U[0] = r.rho + Up[0];
+  U[1] = Up[1];
+  U[2] = Up[2];
+  U[3] = Up[3];
+  U[4] = r.E + Up[4];
+}
+
+// ------------------------------------------------------------------------------------------
+// K1 (FP32 form): U' and its broken gradient to the faces in FP32, momentum to the faces in FP64
+// ------------------------------------------------------------------------------------------
+template <int P, bool VISC>
+__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass32(const double *__restrict__ X,
+                                                             const float *__restrict__ geo32,
+                                                             float *__restrict__ face32,
+                                                             double *__restrict__ facem, int64_t E,
+                                                             OpsT<float> ops, OpsT<double> opsd, Ref32 ref) {
+  using C = Cfg<P>;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int NG = VISC ? 15 : 1;
+  __shared__ float sU[EPB][5][NS];
+  __shared__ double sM[EPB][3][NS];
+  __shared__ float sG[EPB][NG][NS];
+  const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const bool act = e < E;
+  const int i0 = t % N, i1 = (t / N) % N, i2 = t / (N * N);
+  if (act) {
+    const double x0 = X[(e * 5 + 0) * NS + t], x4 = X[(e * 5 + 4) * NS + t];
+    sU[slot][0][t] = float(x0 - ref.rho_d);
+    sU[slot][4][t] = float(x4 - ref.E_d);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double m = X[(e * 5 + 1 + i) * NS + t];
+      sU[slot][1 + i][t] = float(m);
+      sM[slot][i][t] = m;
+    }
+  }
+  __syncthreads();
+  if (VISC && act) {
+    float ja[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = geo32[(e * 10 + c) * NS + t];
+    const float iJ = geo32[(e * 10 + 9) * NS + t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      float d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        d0 += ops.D[i0 * N + c] * sU[slot][v][c + N * (i1 + N * i2)];
+        d1 += ops.D[i1 * N + c] * sU[slot][v][i0 + N * (c + N * i2)];
+        d2 += ops.D[i2 * N + c] * sU[slot][v][i0 + N * (i1 + N * c)];
+      }
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) sG[slot][(ii * 5 + v) % NG][t] = iJ * (ja[ii] * d0 + ja[3 + ii] * d1 + ja[6 + ii] * d2);
+    }
+  }
+  __syncthreads();
+  if (!act) return;
+  for (int fp = t; fp < NF; fp += NS) {
+    const int f = fp / NFP, kk = fp - f * NFP;
+    const int a = kk % N, b = kk / N, d = f >> 1;
+    const float *ell = (f & 1) ? ops.lp : ops.lm;
+    const double *elld = (f & 1) ? opsd.lp : opsd.lm;
+    float *dst = face32 + ((e * 6 + f) * 20) * NFP + kk;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      float acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += ell[c] * sU[slot][v][line_pt<N>(d, c, a, b)];
+      dst[v * NFP] = acc;
+    }
+    if (VISC) {
+#pragma unroll 5
+      for (int g = 0; g < 15; ++g) {
+        float acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][g % NG][line_pt<N>(d, c, a, b)];
+        dst[(5 + g) * NFP] = acc;
+      }
+    }
+    double *dm = facem + ((e * 6 + f) * 3) * NFP + kk;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += elld[c] * sM[slot][i][line_pt<N>(d, c, a, b)];
+      dm[i * NFP] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// K2 (FP32 form): common jump and flux per face point. Outputs
+//   fout32 [F][9][Nfp]: J' = (U'_R - U'_L)/2 (5), owner's momentum flux (3), reduced energy (1)
+//   foutm  [F][Nfp]   : owner's mass flux (FP64)
+// ------------------------------------------------------------------------------------------
+template <int P, bool VISC>
+__global__ __launch_bounds__(256) void k_face32(const float *__restrict__ face32, const double *__restrict__ facem,
+                                                const double *__restrict__ fgeo, const FaceRec *__restrict__ ftab,
+                                                int64_t F, Phys<float> ph, Ref32 ref, int flux,
+                                                float *__restrict__ fout32, double *__restrict__ foutm) {
+  constexpr int N = P + 1, NFP = N * N;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t fc = gid / NFP;
+  if (fc >= F) return;
+  const int kk = (int)(gid - fc * NFP);
+  const FaceRec r = ftab[fc];
+  const int fL = r.code & 7, fR = (r.code >> 3) & 7;
+  const bool swp = (r.code >> 6) & 1, flu = (r.code >> 7) & 1, flv = (r.code >> 8) & 1;
+  const int a = kk % N, b = kk / N;
+  const int uu = swp ? b : a, vv = swp ? a : b;
+  const int kr = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
+  const float *srcL = face32 + (((int64_t)r.eL * 6 + fL) * 20) * NFP + kk;
+  const float *srcR = face32 + (((int64_t)r.eR * 6 + fR) * 20) * NFP + kr;
+  const double *mL = facem + (((int64_t)r.eL * 6 + fL) * 3) * NFP + kk;
+  const double *mR = facem + (((int64_t)r.eR * 6 + fR) * 3) * NFP + kr;
+  const double *fg = fgeo + (fc * 4) * NFP + kk;
+  float UL[5], UR[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    UL[v] = srcL[v * NFP];
+    UR[v] = srcR[v * NFP];
+  }
+  const double Nd[3] = {fg[0], fg[NFP], fg[2 * NFP]};
+  // central mass flux in FP64: (m_L + m_R)/2 . N
+  const double fc_rho = 0.5 * ((mL[0] + mR[0]) * Nd[0] + (mL[NFP] + mR[NFP]) * Nd[1] + (mL[2 * NFP] + mR[2 * NFP]) * Nd[2]);
+  const float NL[3] = {float(Nd[0]), float(Nd[1]), float(Nd[2])};
+  const float nm = sqrtf(NL[0] * NL[0] + NL[1] * NL[1] + NL[2] * NL[2]);
+  const float inm = 1.0f / nm;
+  const float nh[3] = {NL[0] * inm, NL[1] * inm, NL[2] * inm};
+  float Fr[5];
+  riemann32(UL, UR, nh, ph, ref, flux, Fr);
+  if (VISC) {
+    const float sig = float(fg[3 * NFP]);
+    float GI[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        GI[i][v] = 0.5f * (srcL[(5 + i * 5 + v) * NFP] + srcR[(5 + i * 5 + v) * NFP]) + sig * NL[i] * (UR[v] - UL[v]);
+    float UCp[5], UC[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) UCp[v] = 0.5f * (UL[v] + UR[v]);
+    full_state(UCp, ref, UC);
+    float Fv[3][5];
+    visc_flux(UC, GI, ph, Fv);
+#pragma unroll
+    for (int v = 1; v < 5; ++v) Fr[v] -= Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
+  }
+  float *dst = fout32 + (fc * 9) * NFP + kk;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) dst[v * NFP] = 0.5f * (UR[v] - UL[v]);
+#pragma unroll
+  for (int v = 1; v < 5; ++v) dst[(4 + v) * NFP] = nm * Fr[v];
+  foutm[fc * NFP + kk] = fc_rho + double(nm * Fr[0]);
+}
+
+// ------------------------------------------------------------------------------------------
+// K3 (FP32 form): corrected gradient, reduced fluxes, divergence + correction in FP32 for
+// momentum and reduced energy, in FP64 for mass; R_E = R''_E + H_r R_rho; RK update in FP64.
+// ------------------------------------------------------------------------------------------
+template <int P, bool VISC>
+__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
+    const double *__restrict__ X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
+    const float *__restrict__ fout32, const double *__restrict__ foutm, int64_t E, OpsT<float> ops,
+    OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *__restrict__ out0,
+    double *__restrict__ reg1, double *__restrict__ reg2) {
+  using C = Cfg<P>;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int R = (NF + NS - 1) / NS;
+  constexpr int NJ = (VISC ? 9 : 4) * NF;  // [4][NF] flux (mom 3, reduced energy), [5][NF] jumps
+  __shared__ float sUall[EPB][5 * NS];     // U', later 4 components of the transformed flux
+  __shared__ double sMall[EPB][NS];        // transformed mass flux of one direction
+  __shared__ float sJall[EPB][NJ];
+  __shared__ double sJmall[EPB][NF];       // mass flux along +xi_d, then its jump
+  const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const bool act = e < E;
+  const int idx[3] = {t % N, (t / N) % N, t / (N * N)};
+  float *sU = sUall[slot];
+  double *sM = sMall[slot];
+  float *sJ = sJall[slot];
+  double *sJm = sJmall[slot];
+  const int64_t base = e * 5 * NS + t;
+  double Xd[5], jad[9], iJd = 0, r1[5], r2[5];
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Xd[v] = X[base + v * NS];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) jad[c] = geo[(e * 10 + c) * NS + t];
+    iJd = geo[(e * 10 + 9) * NS + t];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int fp = t + r * NS;
+      if (fp < NF) {
+        const int f = fp / NFP, kk = fp - f * NFP;
+        const FaceRef fr = fref[e * 6 + f];
+        const int a = kk % N, b = kk / N;
+        const bool swp = (fr.code >> 3) & 1, flu = (fr.code >> 4) & 1, flv = (fr.code >> 5) & 1;
+        const int uu = swp ? b : a, vv = swp ? a : b;
+        const int kc = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
+        const float *src = fout32 + ((int64_t)fr.fid * 9) * NFP + kc;
+        const bool owner = (fr.code >> 6) & 1;
+        const float sgn = owner ? 1.0f : -1.0f;
+        const float sfl = (f & 1) ? sgn : -sgn;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sJ[c * NF + fp] = sfl * src[(5 + c) * NFP];
+        if (VISC) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) sJ[(4 + c) * NF + fp] = sgn * src[c * NFP];
+        }
+        sJm[fp] = double(sfl) * foutm[(int64_t)fr.fid * NFP + kc];
+      }
+    }
+    sU[0 * NS + t] = float(Xd[0] - ref.rho_d);
+    sU[1 * NS + t] = float(Xd[1]);
+    sU[2 * NS + t] = float(Xd[2]);
+    sU[3 * NS + t] = float(Xd[3]);
+    sU[4 * NS + t] = float(Xd[4] - ref.E_d);
+  }
+  __syncthreads();
+  float F[3][5];  // [direction][component]: 0 unused, 1-3 momentum, 4 reduced energy
+  double Fm[3];   // transformed mass flux per direction (FP64)
+  if (act) {
+    float Up[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Up[v] = sU[v * NS + t];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float ei[3] = {float(i == 0), float(i == 1), float(i == 2)};
+      float un_, c_, pp_, hp_;
+      reduced_flux_n(Up, ei, ph, ref, F[i], un_, c_, pp_, hp_);
+    }
+    if (VISC) {
+      float ja[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) ja[c] = float(jad[c]);
+      const float iJ = float(iJd);
+      float dU[3][5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        float d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+          d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+          d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+        }
+        dU[0][v] = d0;
+        dU[1][v] = d1;
+        dU[2][v] = d2;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
+        const int kk = idx[u] + N * idx[w];
+        const float cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          dU[d][v] += sJ[(4 + v) * NF + (2 * d) * NFP + kk] * cL + sJ[(4 + v) * NF + (2 * d + 1) * NFP + kk] * cR;
+      }
+      float G[3][5];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) G[i][v] = iJ * (ja[i] * dU[0][v] + ja[3 + i] * dU[1][v] + ja[6 + i] * dU[2][v]);
+      float Uf[5];
+      full_state(Up, ref, Uf);
+      float Fv[3][5];
+      visc_flux(Uf, G, ph, Fv);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int v = 1; v < 5; ++v) F[i][v] -= Fv[i][v];
+    }
+    // transformed fluxes per direction
+#pragma unroll
+    for (int v = 1; v < 5; ++v) {
+      const float f0 = F[0][v], f1 = F[1][v], f2 = F[2][v];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        F[d][v] = float(jad[d * 3 + 0]) * f0 + float(jad[d * 3 + 1]) * f1 + float(jad[d * 3 + 2]) * f2;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Fm[d] = jad[d * 3 + 0] * Xd[1] + jad[d * 3 + 1] * Xd[2] + jad[d * 3 + 2] * Xd[3];
+    if (st.mode == kModeLSRK) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+    } else if (st.mode == kModeRK4) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+        r2[v] = out0[base + v * NS];
+      }
+    }
+  }
+  float div[5] = {0, 0, 0, 0, 0};
+  double divm = 0;
+  float *sF = sU;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int v = 1; v < 5; ++v) sF[(v - 1) * NS + t] = F[d][v];
+      sM[t] = Fm[d];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          const int id = d == 0 ? c + N * (idx[1] + N * idx[2])
+                                : (d == 1 ? idx[0] + N * (c + N * idx[2]) : idx[0] + N * (idx[1] + N * c));
+          acc += ops.D[idx[d] * N + c] * sF[v * NS + id];
+        }
+        div[1 + v] += acc;
+      }
+      {
+        double acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          const int id = d == 0 ? c + N * (idx[1] + N * idx[2])
+                                : (d == 1 ? idx[0] + N * (c + N * idx[2]) : idx[0] + N * (idx[1] + N * c));
+          acc += opsd.D[idx[d] * N + c] * sM[id];
+        }
+        divm += acc;
+      }
+      for (int fp = t; fp < 2 * NFP; fp += NS) {
+        const int f = 2 * d + fp / NFP, kk = fp % NFP;
+        const int a = kk % N, b = kk / N;
+        const float *ell = (f & 1) ? ops.lp : ops.lm;
+        const double *elld = (f & 1) ? opsd.lp : opsd.lm;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float acc = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) acc += ell[c] * sF[v * NS + line_pt<N>(d, c, a, b)];
+          sJ[v * NF + f * NFP + kk] -= acc;
+        }
+        double acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) acc += elld[c] * sM[line_pt<N>(d, c, a, b)];
+        sJm[f * NFP + kk] -= acc;
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
+      const int kk = idx[u] + N * idx[w];
+      const float cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) div[1 + v] += sJ[v * NF + (2 * d) * NFP + kk] * cL + sJ[v * NF + (2 * d + 1) * NFP + kk] * cR;
+      divm += sJm[(2 * d) * NFP + kk] * opsd.gcL[idx[d]] + sJm[(2 * d + 1) * NFP + kk] * opsd.gcR[idx[d]];
+    }
+  }
+  if (!act) return;
+  double Rv[5];
+  Rv[0] = -divm * iJd;
+  Rv[1] = -double(div[1]) * iJd;
+  Rv[2] = -double(div[2]) * iJd;
+  Rv[3] = -double(div[3]) * iJd;
+  Rv[4] = -double(div[4]) * iJd + ref.H_d * Rv[0];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double Rr = Rv[v];
+    const int64_t o = base + v * NS;
+    if (st.mode == kModeResidual) {
+      out0[o] = Rr;
+    } else if (st.mode == kModeLSRK) {
+      const double du = st.a * r1[v] + st.dt * Rr;
+      reg1[o] = du;
+      out0[o] = Xd[v] + st.b * du;
+    } else {
+      const double acc = r1[v] + st.w * Rr;
+      if (!st.last) {
+        reg1[o] = acc;
+        reg2[o] = r2[v] + st.cdt * Rr;
+      } else {
+        out0[o] = r2[v] + st.dt * acc;
+      }
+    }
+  }
+}
+
+#define HIPCHK32(call)                                           \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) {                                      \
+      err = std::string(#call) + ": " + hipGetErrorString(e_);   \
+      return -3;                                                 \
+    }                                                            \
+  } while (0)
+
+template <int P, bool VISC>
+int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
+               double *ms, std::string &err) {
+  using C = Cfg<P>;
+  OpsT<float> ops;
+  OpsT<double> opsd;
+  for (int i = 0; i < kMaxN * kMaxN; ++i) {
+    ops.D[i] = float(dm.ops.D[i]);
+    opsd.D[i] = dm.ops.D[i];
+  }
+  for (int i = 0; i < kMaxN; ++i) {
+    ops.lm[i] = float(dm.ops.lm[i]);
+    ops.lp[i] = float(dm.ops.lp[i]);
+    ops.gcL[i] = float(dm.ops.gcL[i]);
+    ops.gcR[i] = float(dm.ops.gcR[i]);
+    opsd.lm[i] = dm.ops.lm[i];
+    opsd.lp[i] = dm.ops.lp[i];
+    opsd.gcL[i] = dm.ops.gcL[i];
+    opsd.gcR[i] = dm.ops.gcR[i];
+  }
+  Phys<float> ph{float(dm.phys.gamma), float(dm.phys.gamma - 1.0), float(dm.phys.mu), float(dm.phys.kappa)};
+  Ref32 ref;
+  ref.rho_d = dm.ref_rho;
+  ref.E_d = dm.ref_p / (dm.phys.gamma - 1.0);
+  ref.H_d = (ref.E_d + dm.ref_p) / dm.ref_rho;
+  ref.rho = float(ref.rho_d);
+  ref.E = float(ref.E_d);
+  ref.H = float(ref.H_d);
+  ref.p = float(dm.ref_p);
+  const int64_t blocks = (dm.E + C::EPB - 1) / C::EPB;
+  const int64_t fblocks = (dm.F * C::NFP + 255) / 256;
+  hipStream_t s = (hipStream_t)dm.stream;
+  hipEvent_t ev[4];
+  if (ms) {
+    for (int i = 0; i < 4; ++i) HIPCHK32(hipEventCreate(&ev[i]));
+    HIPCHK32(hipEventRecord(ev[0], s));
+  }
+  hipLaunchKernelGGL((k_prepass32<P, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X, (const float *)dm.geo32,
+                     (float *)dm.face32, (double *)dm.facem, dm.E, ops, opsd, ref);
+  HIPCHK32(hipGetLastError());
+  if (ms) HIPCHK32(hipEventRecord(ev[1], s));
+  hipLaunchKernelGGL((k_face32<P, VISC>), dim3((unsigned)fblocks), dim3(256), 0, s, (const float *)dm.face32,
+                     (const double *)dm.facem, (const double *)dm.fgeo, dm.ftab, dm.F, ph, ref, dm.flux,
+                     (float *)dm.fout32, (double *)dm.foutm);
+  HIPCHK32(hipGetLastError());
+  if (ms) HIPCHK32(hipEventRecord(ev[2], s));
+  hipLaunchKernelGGL((k_volume32<P, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X, (const double *)dm.geo,
+                     dm.fref, (const float *)dm.fout32, (const double *)dm.foutm, dm.E, ops, opsd, ph, ref, st, out0,
+                     reg1, reg2);
+  HIPCHK32(hipGetLastError());
+  if (ms) {
+    HIPCHK32(hipEventRecord(ev[3], s));
+    HIPCHK32(hipEventSynchronize(ev[3]));
+    for (int i = 0; i < 3; ++i) {
+      float tms = 0;
+      HIPCHK32(hipEventElapsedTime(&tms, ev[i], ev[i + 1]));
+      ms[i] += tms;
+    }
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  }
+  return 0;
+}
+
+template <bool VISC>
+int launch32_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
+               std::string &err) {
+  switch (dm.p) {
+    case 0: return launch32_t<0, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 1: return launch32_t<1, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 2: return launch32_t<2, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 3: return launch32_t<3, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 4: return launch32_t<4, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 5: return launch32_t<5, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 6: return launch32_t<6, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 7: return launch32_t<7, VISC>(dm, X, st, o, r1, r2, ms, err);
+    default: err = "p out of range"; return -5;
+  }
+}
+
+}  // namespace
+
+namespace frk {
+// Enqueue one stage of the FP32 form; returns 0 or a negative FR_ERR_* code with `err` set.
+int launch_stage32(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
+                   std::string &err) {
+  return dm.viscous ? launch32_p<true>(dm, X, st, o, r1, r2, ms, err) : launch32_p<false>(dm, X, st, o, r1, r2, ms, err);
+}
+}  // namespace frk

@@ -36,6 +36,7 @@ class fr_mesh_desc(ctypes.Structure):
         ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("mu", ctypes.c_double),
         ("br2_eta", ctypes.c_double), ("flux", ctypes.c_int32), ("prec", ctypes.c_int32),
         ("check_finite", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("ref_rho", ctypes.c_double), ("ref_p", ctypes.c_double),
     ]
 
 
@@ -65,9 +66,10 @@ def load():
     L.fr_profile_stages.argtypes = [P, f64, i32, i32, P]
     L.fr_mesh_geometry_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, P, P, P, P]
     L.fr_basis_host.argtypes = [i32, P, P, P, P, P]
+    L.fr_kinetic_energy.argtypes = [P, P]
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
-                 "fr_mesh_geometry_host", "fr_basis_host"):
+                 "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -84,14 +86,15 @@ def _current_stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep):
+def _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, ref=(1.0, 0.0)):
     ev = np.ascontiguousarray(mesh.elem_vert, dtype=np.int64)
     nodes = np.ascontiguousarray(mesh.elem_nodes, dtype=np.float64)
     keep.extend([ev, nodes])
     return fr_mesh_desc(p=int(p), q=int(mesh.q), n_elem=int(ev.shape[0]), elem_vert=ev.ctypes.data,
                         elem_nodes=nodes.ctypes.data, gamma=gamma, prandtl=prandtl, mu=mu,
                         br2_eta=eta, flux=FLUX[flux], prec=PREC[prec],
-                        check_finite=int(bool(check_finite)), reserved=0)
+                        check_finite=int(bool(check_finite)), reserved=0,
+                        ref_rho=float(ref[0]), ref_p=float(ref[1]))
 
 
 def geometry_host(mesh, p: int, eta: float = 6.0):
@@ -122,13 +125,13 @@ class FRMesh:
 
     def __init__(self, mesh, p: int, *, mu: float = 0.0, gamma: float = 1.4, prandtl: float = 0.72,
                  eta: float = 6.0, flux: str = "rusanov", prec: str = "fp64", check_finite: bool = False,
-                 stream=None):
+                 stream=None, ref_rho: float = 1.0, ref_p: float = 0.0):
         L = load()
         self.p = int(p)
         self.Ns = (self.p + 1) ** 3
         self.E = int(mesh.elem_vert.shape[0])
         keep = []
-        d = _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep)
+        d = _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, (ref_rho, ref_p))
         self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
         h = ctypes.c_void_p()
         _check(L.fr_mesh_create(ctypes.byref(d), self._stream, ctypes.byref(h)))
@@ -193,6 +196,12 @@ class FRMesh:
         ms = np.zeros(3)
         _check(load().fr_profile_stages(self.h, float(dt), SCHEME[scheme], int(n_steps), ms.ctypes.data))
         return tuple(float(x) for x in ms)
+
+    def kinetic_energy(self):
+        """(E_k, dE_k/dt) of the current state, volume averaged (fr_kinetic_energy)."""
+        out = np.zeros(2)
+        _check(load().fr_kinetic_energy(self.h, out.ctypes.data))
+        return float(out[0]), float(out[1])
 
     def info(self):
         E, ns, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
