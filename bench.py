@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"],
                     help="fp32: FP32 operators and fluxes with FP64 state and mass equation")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip timing the FP32 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer once (a known-size "
                          "dispatch that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -165,6 +166,47 @@ def main():
     stage_bytes = ab["stage_min"] * mesh.n_elem
     ok = bool(np.isfinite(g.get_state()).all())
 
+    # HBM traffic of the dominant kernel from the committed rocprofv3 summary, only while the
+    # kernel sources still match the ones the counters were taken on
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_n{args.n}_p{args.p}_{args.prec}"
+                         f"{'_affine' if args.affine else ''}.json")
+    if os.path.exists(tfile):
+        from paper_2308_06605_amd import profiling
+
+        with open(tfile) as f:
+            ts = json.load(f)
+        kname = {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume"}[dominant]
+        if args.prec == "fp32":
+            kname += "32"
+        rec = ts["kernels"].get(kname)
+        if ts.get("kernel_source_hash") == profiling.kernel_source_hash() and rec:
+            traffic = rec["fetch_bytes"] + rec["write_bytes"]
+
+    variants = {}
+    if args.prec == "fp64" and not args.no_variants:
+        # the FP32 form on the same mesh and state, timed the same way
+        g.close()
+        g32 = fr.FRMesh(mesh, args.p, mu=mu, flux=args.flux, prec="fp32", ref_rho=1.0, ref_p=p0)
+        g32.set_state(U)
+        for _ in range(args.warmup):
+            g32.rk_step(args.dt, args.scheme, 1)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g32.rk_step(args.dt, args.scheme, args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms32 = e0.elapsed_time(e1) / args.steps
+        k32 = dict(zip(("prepass", "face", "volume"), g32.profile_stages(args.dt, args.scheme, 2)))
+        ab32 = algorithmic_bytes(args.p, "fp32")
+        variants["fp32"] = {
+            "value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32, "speedup_vs_fp64": ms_step / ms32,
+            "kernel_ms": k32,
+            "kernel_gbs": {k: ab32[k] * mesh.n_elem / (k32[k] * 1e-3) / 1e9 for k in k32},
+            "finite": bool(np.isfinite(g32.get_state()).all()),
+            "dtype": "f32 operators and fluxes, f64 state, RK registers and mass equation"}
+        g32.close()
+
     cpu = None
     if not args.no_cpu:
         try:
@@ -191,14 +233,15 @@ def main():
         "config": {"workload": wl, "n_elem": mesh.n_elem, "dof": dof, "p": args.p,
                    "stages_per_step": stages, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": {"prepass": "k_prepass", "face": "k_face",
-                                "volume": "k_volume"}[dominant],
+                                "volume": "k_volume"}[dominant] + ("32" if args.prec == "fp32" else ""),
                      "bytes_per_launch": ab[dominant] * mesh.n_elem,
                      "mean_launch_ms": kms[dominant]},
         "stage": {"kernel_ms": kms, "kernel_gbs": gbs, "stage_ms": stage_ms,
                   "stage_min_bytes": stage_bytes,
                   "stage_min_bytes_frac_of_hbm": stage_bytes / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "variants": variants,
         "cpu_baseline": cpu,
         "setup_s": t_setup,
         "wall_s_timed": t_wall,

@@ -1,0 +1,93 @@
+"""Turn rocprofv3 counter CSVs into a per-kernel HBM traffic summary.
+
+Usage (after two `rocprofv3 --pmc` runs of bench.py with --copy-calibration, one collecting
+FETCH_SIZE and one WRITE_SIZE):
+
+  python -m paper_2308_06605_amd.profiling --fetch <dir>/run_counter_collection.csv \\
+      --write <dir>/run_counter_collection.csv --calib-bytes 268435456 --out <summary.json>
+
+Each counter is averaged per kernel over its dispatches (KiB per dispatch) and scaled by the
+factor that makes the calibration copy (a plain device-to-device copy of --calib-bytes bytes)
+read and write exactly that many bytes. The summary records a hash of the kernel sources, so a
+reader can tell whether the counters still describe the current kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("fr_kernels.hip", "fr_kernels32.hip", "fr_device.h", "fr_internal.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """'void (anonymous namespace)::k_face32<3, true>(...)' -> 'k_face32'"""
+    base = name.replace("void ", "").replace("(anonymous namespace)::", "")
+    return base.split("<")[0].split("(")[0].strip()
+
+
+def per_kernel_kib(path: str, counter: str):
+    vals = collections.defaultdict(list)
+    grid = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            k = short_name(r["Kernel_Name"])
+            vals[(k, r["Grid_Size"])].append(float(r["Counter_Value"]))
+            grid[(k, r["Grid_Size"])] = int(r["Grid_Size"])
+    return {key: sum(v) / len(v) for key, v in vals.items()}
+
+
+def summarize(fetch_csv: str, write_csv: str, calib_bytes: int) -> dict:
+    fetch = per_kernel_kib(fetch_csv, "FETCH_SIZE")
+    write = per_kernel_kib(write_csv, "WRITE_SIZE")
+    # the calibration copy: the copy dispatch with the largest write
+    copies = [k for k in write if "copyBuffer" in k[0]]
+    if not copies:
+        raise SystemExit("no calibration copy dispatch found")
+    cal = max(copies, key=lambda k: write[k])
+    f_scale = calib_bytes / 1024.0 / fetch[cal]
+    w_scale = calib_bytes / 1024.0 / write[cal]
+    kernels = {}
+    for key in fetch:
+        name = key[0]
+        if not name.startswith("k_") or key not in write:
+            continue
+        kernels[name] = {
+            "fetch_bytes": fetch[key] * 1024.0 * f_scale,
+            "write_bytes": write[key] * 1024.0 * w_scale,
+        }
+    return {"kernel_source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+            "calibration_copy_bytes": calib_bytes, "kernels": kernels}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--calib-bytes", type=int, required=True)
+    ap.add_argument("--command", default="", help="the rocprofv3 command, recorded in the summary")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    s = summarize(a.fetch, a.write, a.calib_bytes)
+    s["command"] = a.command
+    with open(a.out, "w") as f:
+        json.dump(s, f, indent=1)
+    print(json.dumps(s, indent=1))
+
+
+if __name__ == "__main__":
+    main()
