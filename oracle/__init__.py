@@ -58,6 +58,9 @@ def _load():
     L.ora_inviscid_flux.argtypes = [f64, P, P, P]
     L.ora_viscous_flux.argtypes = [f64, f64, f64, P, P, P]
     L.ora_rk_scalar.argtypes = [i32, i32, f64, f64, f64, i32, P]
+    L.ora_n_features.argtypes = [P]
+    L.ora_sgs_features.argtypes = [P, P, P]
+    L.ora_set_eddy_viscosity.argtypes = [P, P, f64]
     _lib = L
     return L
 
@@ -128,6 +131,27 @@ class Oracle:
         if rc:
             raise RuntimeError("oracle rk_step failed: " + _load().ora_last_error().decode())
         return U
+
+    def set_eddy_viscosity(self, nu_t, prandtl_t: float = 0.9):
+        """Per-element eddy kinematic viscosity [E] (>= 0) for every later residual, or None."""
+        if nu_t is None:
+            self._nut = None
+            rc = _load().ora_set_eddy_viscosity(self.h, None, prandtl_t)
+        else:
+            self._nut = np.ascontiguousarray(nu_t, dtype=np.float64)
+            assert self._nut.shape == (self.E,)
+            rc = _load().ora_set_eddy_viscosity(self.h, _ptr(self._nut), prandtl_t)
+        if rc:
+            raise RuntimeError("oracle: " + _load().ora_last_error().decode())
+
+    def sgs_features(self, U: np.ndarray) -> np.ndarray:
+        """Inputs of the learned closure per (active) element: [NA][(p+1)^3 + 4]."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (self.E, 5, self.Ns)
+        nf = _load().ora_n_features(self.h)
+        out = np.empty((self.NA, nf))
+        _load().ora_sgs_features(self.h, _ptr(U), _ptr(out))
+        return out
 
     def sol_coords(self) -> np.ndarray:
         X = np.empty((self.NA, 3, self.Ns))

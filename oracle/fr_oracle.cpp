@@ -327,10 +327,17 @@ void roe(const T UL[5], const T UR[5], const T n[3], T gamma, T F[5]) {
 
 // Viscous flux Fv[i][v] from the state U and the gradient of the conserved variables,
 // G[i][v] = d U_v / d x_i.
+//
+// Eddy viscosity (learned sub-grid closure): mut = rho * nu_t is added to mu in the stress and
+// mut / Pr_t to mu / Pr in the heat flux (an eddy-viscosity reading of the "LES sub-grid scale
+// models" the solver supports; the paper gives no model). mut = 0 reproduces the plain flux
+// bit for bit.
 template <class T>
-void viscous_flux(const T U[5], const T G[3][5], const Gas<T> &gas, T Fv[3][5]) {
-  const T gamma = gas.gamma, mu = gas.mu;
-  const T kappa = mu * gamma / (gas.prandtl * (gamma - 1));
+void viscous_flux(const T U[5], const T G[3][5], const Gas<T> &gas, T Fv[3][5], T mut = T(0),
+                  T prandtl_t = T(1)) {
+  const T gamma = gas.gamma, mu = gas.mu + mut;
+  const T kappa = gas.mu * gamma / (gas.prandtl * (gamma - 1)) +
+                  (mut != T(0) ? mut * gamma / (prandtl_t * (gamma - 1)) : T(0));
   T rho = U[0];
   T u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
   T e = U[4] / rho;
@@ -433,6 +440,10 @@ struct Iface {
   virtual int sol_coords(double *xyz) = 0;
   virtual int geometry(double *Ja, double *detJ, double *Nf, double *Jf) = 0;
   virtual int connectivity(int64_t *nbr, int32_t *nface, int32_t *owner, int32_t *perm) = 0;
+  virtual int sgs_features(const double *U, double *feat) = 0;
+  virtual int n_features() const = 0;
+  virtual int set_eddy_viscosity(const double *nu, double prandtl_t) = 0;
+  virtual std::string last_err() const = 0;
 };
 
 template <class T>
@@ -458,6 +469,8 @@ struct Oracle : Iface {
   vector<T> Jf;    // [slot][6][Nfp]    |J| interpolated to face points
   vector<T> Xs;    // [slot][3][Ns]     solution point coordinates
   int nthreads;
+  vector<T> nut;          // [E] eddy kinematic viscosity per element; empty = none
+  T prandtl_t = T(0.9);   // turbulent Prandtl number
 
   // per-stage scratch over stored elements
   vector<T> Uf, Gf, UCf, FIf;  // [slot][6][Nfp][5], [slot][6][Nfp][3][5], ..
@@ -473,6 +486,7 @@ struct Oracle : Iface {
   }
 
   std::string err;
+  std::string last_err() const override { return err; }
 
   // rounding of a long-double metric term to T, optionally moved by one unit in the last place
   T round_geo(long double v, uint64_t key) const {
@@ -753,7 +767,7 @@ struct Oracle : Iface {
 
   // ---- the residual: dU/dt of Eq. (3) with S = 0 ----
   int residual_impl(const vector<T> &Ufull /*[E][5][Ns]*/, T *R /*[n_active][5][Ns]*/) {
-    const bool viscous = gas.mu != T(0);
+    const bool viscous = gas.mu != T(0) || !nut.empty();
     // pass 1: per element, interpolate U and the broken physical gradient to the faces
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
     for (int64_t e = 0; e < E; ++e) {
@@ -830,7 +844,9 @@ struct Oracle : Iface {
                 GI[i][v] = T(0.5) * ((gL + eta * rL) + (gR + eta * rR));
               }
             T Fv[3][5];
-            viscous_flux<T>(UC, GI, gas, Fv);
+            // common eddy viscosity: mean of the two elements' values, density of the common state
+            const T mut = nut.empty() ? T(0) : UC[0] * (nut[e] + nut[eR]) / 2;
+            viscous_flux<T>(UC, GI, gas, Fv, mut, prandtl_t);
             for (int v = 0; v < 5; ++v) Fvn[v] = Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
           }
           for (int v = 0; v < 5; ++v) {
@@ -888,7 +904,8 @@ struct Oracle : Iface {
               G[i][v] = iJ * g;
             }
           T Fv[3][5];
-          viscous_flux<T>(Us, G, gas, Fv);
+          const T mut = nut.empty() ? T(0) : Us[0] * nut[e];
+          viscous_flux<T>(Us, G, gas, Fv, mut, prandtl_t);
           for (int i = 0; i < 3; ++i)
             for (int v = 0; v < 5; ++v) F[i][v] -= Fv[i][v];
         }
@@ -922,6 +939,109 @@ struct Oracle : Iface {
       for (int v = 0; v < 5; ++v)
         for (int s = 0; s < Ns; ++s) R[(ia * 5 + v) * Ns + s] = -div[v * Ns + s] / detJ[sl * Ns + s];
     }
+    return 0;
+  }
+
+  // ---- per-element inputs of the learned eddy-viscosity closure ----
+  // From the element's own velocity polynomial u_j (nodal values m_j / rho at the solution
+  // points):
+  //  * modal energies e_k = (1/8) * 1/2 * sum_j uhat_{j,k}^2 over the orthonormal tensor
+  //    Legendre modes k = (a, b, c) of the reference element (uhat by Gauss quadrature, exact for
+  //    a degree-p polynomial), so that sum_k e_k is the reference-element mean of |u|^2 / 2;
+  //    the constant mode is dropped (Galilean invariance), leaving (p+1)^3 - 1 values;
+  //  * five volume averages over the element of the broken velocity gradient
+  //    A_ij = d u_j / d x_i: s2 = <2 S:S>, w2 = <2 W:W> (S, W its symmetric and antisymmetric
+  //    parts), r = <-tr(A^3) / 3>, th = <tr A>, th2 = <(tr A)^2>.
+  // Features: ln(e_k + eps) for each kept mode, then ln(s2 + eps) / 2, ln(w2 + eps) / 2,
+  // r / (s2 + eps)^(3/2), th / (s2 + eps)^(1/2), th2 / (s2 + eps), with eps = 1e-12.
+  int n_features() const override { return Ns - 1 + 5; }
+
+  int sgs_features(const double *Uin, double *feat) override {
+    const int NF = n_features();
+    const T eps = T(1e-12);
+    vector<T> L(n * n);  // L[a*n + i] = orthonormal Legendre a at xs_i, times w_i
+    for (int a = 0; a < n; ++a)
+      for (int i = 0; i < n; ++i) {
+        T P, dP;
+        legendre<T>(a, B.xs[i], P, dP);
+        L[a * n + i] = std::sqrt(T(2 * a + 1) / 2) * P * B.ws[i];
+      }
+    const int64_t NA = (int64_t)active.size();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t ia = 0; ia < NA; ++ia) {
+      const int64_t e = active[ia];
+      const int64_t sl = slot[e];
+      vector<T> u(3 * Ns), du(3 * 3 * Ns);
+      for (int s = 0; s < Ns; ++s) {
+        T rho = T(Uin[(e * 5 + 0) * Ns + s]);
+        for (int j = 0; j < 3; ++j) u[j * Ns + s] = T(Uin[(e * 5 + 1 + j) * Ns + s]) / rho;
+      }
+      for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < 3; ++j) ref_deriv(d, &u[j * Ns], &du[(d * 3 + j) * Ns]);
+      double *out = feat + ia * NF;
+      int col = 0;
+      for (int c = 0; c < n; ++c)
+        for (int b = 0; b < n; ++b)
+          for (int a = 0; a < n; ++a) {
+            if (a == 0 && b == 0 && c == 0) continue;
+            T ek = 0;
+            for (int j = 0; j < 3; ++j) {
+              T uh = 0;
+              for (int kk = 0; kk < n; ++kk)
+                for (int jj = 0; jj < n; ++jj)
+                  for (int ii = 0; ii < n; ++ii)
+                    uh += L[a * n + ii] * L[b * n + jj] * L[c * n + kk] * u[j * Ns + ii + n * (jj + n * kk)];
+              ek += uh * uh;
+            }
+            ek = ek / 16;
+            out[col++] = double(std::log(ek + eps));
+          }
+      T vol = 0, s2 = 0, w2 = 0, r = 0, th = 0, th2 = 0;
+      for (int kk = 0; kk < n; ++kk)
+        for (int jj = 0; jj < n; ++jj)
+          for (int ii = 0; ii < n; ++ii) {
+            const int s = ii + n * (jj + n * kk);
+            const T *ja = &Ja[(sl * Ns + s) * 9];
+            const T dJ = detJ[sl * Ns + s];
+            T A[3][3];
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j) {
+                T g = 0;
+                for (int d = 0; d < 3; ++d) g += ja[d * 3 + i] * du[(d * 3 + j) * Ns + s];
+                A[i][j] = g / dJ;
+              }
+            T ss = 0, ww = 0, t3 = 0;
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j) {
+                T S = (A[i][j] + A[j][i]) / 2, W = (A[i][j] - A[j][i]) / 2;
+                ss += S * S;
+                ww += W * W;
+                for (int k = 0; k < 3; ++k) t3 += A[i][j] * A[j][k] * A[k][i];
+              }
+            T tr = A[0][0] + A[1][1] + A[2][2];
+            T wq = B.ws[ii] * B.ws[jj] * B.ws[kk] * dJ;
+            vol += wq;
+            s2 += wq * 2 * ss;
+            w2 += wq * 2 * ww;
+            r += wq * (-t3 / 3);
+            th += wq * tr;
+            th2 += wq * tr * tr;
+          }
+      s2 /= vol; w2 /= vol; r /= vol; th /= vol; th2 /= vol;
+      out[col++] = double(std::log(s2 + eps) / 2);
+      out[col++] = double(std::log(w2 + eps) / 2);
+      out[col++] = double(r / std::pow(s2 + eps, T(1.5)));
+      out[col++] = double(th / std::sqrt(s2 + eps));
+      out[col++] = double(th2 / (s2 + eps));
+    }
+    return 0;
+  }
+
+  int set_eddy_viscosity(const double *nu, double prt) override {
+    if (!nu) { nut.clear(); return 0; }
+    nut.assign(nu, nu + E);
+    for (auto &x : nut) if (!(x >= 0)) { err = "eddy viscosity must be >= 0"; nut.clear(); return -1; }
+    prandtl_t = T(prt);
     return 0;
   }
 
@@ -1022,6 +1142,19 @@ void *ora_create(int prec, int p, int64_t n_elem, const int64_t *elem_vert, int 
 }
 
 void ora_destroy(void *h) { delete static_cast<Iface *>(h); }
+
+int ora_n_features(void *h) { return static_cast<Iface *>(h)->n_features(); }
+
+// feat: [n_active][n_features] doubles
+int ora_sgs_features(void *h, const double *U, double *feat) { return static_cast<Iface *>(h)->sgs_features(U, feat); }
+
+// nu: [E] per-element eddy kinematic viscosity (>= 0), or NULL to switch the closure off
+int ora_set_eddy_viscosity(void *h, const double *nu, double prandtl_t) {
+  Iface *o = static_cast<Iface *>(h);
+  int rc = o->set_eddy_viscosity(nu, prandtl_t);
+  if (rc) g_err = o->last_err();
+  return rc;
+}
 
 int ora_residual(void *h, const double *U, double *R) { return static_cast<Iface *>(h)->residual(U, R); }
 
