@@ -158,6 +158,87 @@ int fr_mesh_geometry_host(const fr_mesh_desc *desc, double *geo, double *fgeo, i
  * gcL = g_L'(x_a) and gcR = g_R'(x_a) of the DG-equivalent correction functions. */
 int fr_basis_host(int p, double *D, double *lm, double *lp, double *gcL, double *gcR);
 
+/* ==========================================================================================
+ * Learned eddy-viscosity closure (an LES sub-grid scale model; section "ZFR Framework" lists
+ * such models among the solver's physical models without specifying one).
+ *
+ * An eddy kinematic viscosity nu_t >= 0, constant per element, enters the viscous flux as
+ * mu + rho nu_t in the stress and mu/Pr + rho nu_t/Pr_t in the heat flux (gamma/(gamma-1)
+ * times these, acting on d(p/rho)); at a face, nu_t is the mean of the two elements' values
+ * and rho that of the common state. nu_t = 0 reproduces the plain residual. The closure needs
+ * prec = FR_FP64 (FR_ERR_UNSUPPORTED otherwise).
+ *
+ * The model is a per-element network y = softplus(w3 . tanh(W2 tanh(W1 x^ + b1) + b2) + b3),
+ * x^ = (x - mean)/std, 64 units per hidden layer, with nu_t = nu_scale * y. W1, W2 and w3 are
+ * used rounded to bfloat16 (nearest, ties to even) on the matrix cores with float32
+ * accumulation; activations enter the products as the sum of two bfloat16 values (a hi/lo
+ * split, relative representation error <= 2^-17). Biases, standardisation and Adam state are
+ * float32. Parameters are one float32 array in the order W1[64][n_in], b1[64], W2[64][64],
+ * b2[64], w3[64], b3[1] (fr_mlp_n_params(n_in) values).
+ * ========================================================================================== */
+typedef struct fr_mlp_s *fr_mlp_t;
+
+/* Number of features per element for degree p: (p+1)^3 - 1 modal energies + 5 invariants. */
+int fr_sgs_n_features(int p);
+
+/* Features of the handle's current state, device array feat [n_elem][fr_sgs_n_features(p)]
+ * float32, enqueued on the handle's stream. From the element's velocity polynomial u = m/rho:
+ *   ln(e_k + 1e-12) for each orthonormal tensor Legendre mode k = a + n(b + n c) except the
+ *   constant one, e_k = (1/16) sum_j uhat_{j,k}^2 (uhat by Gauss quadrature on the reference
+ *   cube); then, with volume averages <.> over the element of the broken velocity gradient
+ *   A_ij = d u_j/d x_i (S, W its symmetric / antisymmetric parts) and eps = 1e-12:
+ *   ln(<2S:S> + eps)/2, ln(<2W:W> + eps)/2, <-tr(A^3)/3>/(<2S:S> + eps)^(3/2),
+ *   <tr A>/(<2S:S> + eps)^(1/2), <(tr A)^2>/(<2S:S> + eps).
+ * Computed in double precision and rounded to float32 once. */
+int fr_sgs_features(fr_mesh_t m, float *feat);
+
+/* Fixed per-element eddy viscosity nu [n_elem] (>= 0; on_device as above) used by every
+ * later residual and RK stage, with turbulent Prandtl number prandtl_t > 0; nu = NULL turns
+ * the closure off. Replaces an attached model. */
+int fr_set_eddy_viscosity(fr_mesh_t m, const double *nu, int on_device, double prandtl_t);
+
+/* Attach a model: every later residual and RK stage first computes the features of the state
+ * it is evaluated on and nu_t = nu_scale * model(features), then the stage. The model must
+ * have n_in = fr_sgs_n_features(p) and must outlive the attachment; model = NULL detaches. */
+int fr_set_sgs_model(fr_mesh_t m, fr_mlp_t model, double nu_scale, double prandtl_t);
+
+/* The per-element eddy viscosity of the last stage (or the fixed one), host array [n_elem]. */
+int fr_get_eddy_viscosity(fr_mesh_t m, double *nu);
+
+/* Parameter count for n_in inputs. */
+int64_t fr_mlp_n_params(int32_t n_in);
+
+/* Create a network with n_in (1..128) inputs on the current device. params (host, float32,
+ * fr_mlp_n_params values), mean and std (host, n_in values, std > 0) are copied. Adam state
+ * starts at zero. hip_stream as in fr_mesh_create. */
+int fr_mlp_create(int32_t n_in, const float *params, const float *mean, const float *std_dev, void *hip_stream,
+                  fr_mlp_t *out);
+int fr_mlp_destroy(fr_mlp_t net);
+int fr_mlp_set_stream(fr_mlp_t net, void *hip_stream);
+
+/* Replace the parameters (host float32) and reset the Adam state; read them back (waits). */
+int fr_mlp_set_params(fr_mlp_t net, const float *params);
+int fr_mlp_get_params(fr_mlp_t net, float *params);
+
+/* The bfloat16 bit patterns of W1 [64][n_in], W2 [64][64] and w3 [64] as the kernels use them
+ * (host arrays; waits). */
+int fr_mlp_get_bf16(fr_mlp_t net, uint16_t *W1, uint16_t *W2, uint16_t *w3);
+
+/* y [n] = model(X) for device arrays X [n][ldx] float32 (ldx >= n_in) and y [n] float32. */
+int fr_mlp_forward(fr_mlp_t net, const float *X, int64_t n, int64_t ldx, float *y);
+
+/* Loss L = mean_n (y_n - t_n)^2 over device arrays X [n][ldx], t [n], and its gradient with
+ * respect to every parameter (host grad [n_params]; the gradient of a rounded weight is used for
+ * its master). No update. Deterministic (fixed reduction order). Waits. */
+int fr_mlp_loss_grad(fr_mlp_t net, const float *X, int64_t n, int64_t ldx, const float *t, float *grad,
+                     double *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the loss above: the
+ * forward and backward passes, the deterministic gradient reduction and the update of the
+ * float32 masters and their bfloat16 copies. loss (device float, may be NULL) receives L before
+ * the update. Enqueued on the network's stream. */
+int fr_mlp_train_step(fr_mlp_t net, const float *X, int64_t n, int64_t ldx, const float *t, float lr, float *loss);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *fr_last_error(void);
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfr.so")
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("fr_kernels.hip", "fr_kernels32.hip", "fr_host.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("fr_kernels.hip", "fr_kernels32.hip", "fr_mlp.hip", "fr_host.cpp")]
 
 
 def hipcc_command(out: str = LIB) -> list:

@@ -99,9 +99,11 @@ __device__ __forceinline__ void roe(const real UL[5], const real UR[5], const re
   for (int v = 0; v < 5; ++v) F[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * dis[v];
 }
 
-// Viscous flux Fv[i][v] from U and the gradient of the conserved variables G[i][v].
+// Viscous flux Fv[i][v] from U and the gradient of the conserved variables G[i][v], with
+// dynamic viscosity mu and heat-flux coefficient kappa (on d(p/rho)).
 template <typename real>
-__device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], const Phys<real> &ph, real Fv[3][5]) {
+__device__ __forceinline__ void visc_flux_mk(const real U[5], const real G[3][5], real gm1, real mu, real kappa,
+                                             real Fv[3][5]) {
   const real ir = real(1) / U[0];
   const real u[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
   const real e = U[4] * ir;
@@ -111,20 +113,25 @@ __device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], c
 #pragma unroll
     for (int j = 0; j < 3; ++j) du[i][j] = (G[i][1 + j] - u[j] * G[i][0]) * ir;
     const real de = (G[i][4] - e * G[i][0]) * ir;
-    dT[i] = ph.gm1 * (de - (u[0] * du[i][0] + u[1] * du[i][1] + u[2] * du[i][2]));
+    dT[i] = gm1 * (de - (u[0] * du[i][0] + u[1] * du[i][1] + u[2] * du[i][2]));
   }
-  const real lam = real(-2.0 / 3.0) * ph.mu * (du[0][0] + du[1][1] + du[2][2]);
+  const real lam = real(-2.0 / 3.0) * mu * (du[0][0] + du[1][1] + du[2][2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     real tau[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) tau[j] = ph.mu * (du[j][i] + du[i][j]) + (i == j ? lam : real(0));
+    for (int j = 0; j < 3; ++j) tau[j] = mu * (du[j][i] + du[i][j]) + (i == j ? lam : real(0));
     Fv[i][0] = 0;
     Fv[i][1] = tau[0];
     Fv[i][2] = tau[1];
     Fv[i][3] = tau[2];
-    Fv[i][4] = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + ph.kappa * dT[i];
+    Fv[i][4] = tau[0] * u[0] + tau[1] * u[1] + tau[2] * u[2] + kappa * dT[i];
   }
+}
+
+template <typename real>
+__device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], const Phys<real> &ph, real Fv[3][5]) {
+  visc_flux_mk(U, G, ph.gm1, ph.mu, ph.kappa, Fv);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -520,6 +520,21 @@ Ops1D basis_ops(int p) {
   return o;
 }
 
+SgsOps sgs_ops(int p) {
+  frh::Basis B = frh::make_basis(p);
+  SgsOps o;
+  std::memset(&o, 0, sizeof o);
+  const int n = p + 1;
+  for (int a = 0; a < n; ++a)
+    for (int i = 0; i < n; ++i) {
+      frh::LD P, dP;
+      frh::legendre_pair(a, B.xs[i], &P, &dP);
+      o.Lm[a * n + i] = (double)(std::sqrt((frh::LD)(2 * a + 1) / 2) * P * B.ws[i]);
+    }
+  for (int i = 0; i < n; ++i) o.w[i] = (double)B.ws[i];
+  return o;
+}
+
 std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const double *nodes, double eta,
                             HostMesh &H) {
   using frh::LD;

@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+struct fr_mlp_s;
+
 namespace frk {
 
 constexpr int kMaxP = 7;
@@ -20,6 +22,13 @@ struct Ops1D {
   double gcL[kMaxN];        // correction from the face at xi = -1, multiplied by its sign -1:
                             // the derivative of g_L at x_a
   double gcR[kMaxN];        // derivative of g_R at x_a (face at xi = +1)
+};
+
+// Tables of the closure's features: Lm[a*n + i] = orthonormal Legendre a at x_i times the
+// Gauss weight w_i (the modal projection), and the weights w.
+struct SgsOps {
+  double Lm[kMaxN * kMaxN];
+  double w[kMaxN];
 };
 
 struct Ops1Df {
@@ -112,6 +121,13 @@ struct DeviceMesh {
   void *fout32 = nullptr;   // [F][9][Nfp] float: J (5), owner's momentum flux (3), reduced energy flux
   void *foutm = nullptr;    // [F][Nfp] double: owner's mass flux
   double ref_rho = 1.0, ref_p = 0.0;
+  // learned eddy-viscosity closure (FP64 path only)
+  int sgs = 0;                 // 0 off, 1 fixed per-element nu_t, 2 nu_t from the model per stage
+  double *nut = nullptr;       // [E] eddy kinematic viscosity
+  float *feat = nullptr;       // [E][Ns + 4] model inputs
+  fr_mlp_s *model = nullptr;
+  double nu_scale = 0.0, prandtl_t = 0.9;
+  SgsOps sgs_ops;
   int *flag = nullptr;    // non-finite flag
   bool check_finite = false;
   void *stream = nullptr;
@@ -138,6 +154,16 @@ int launch_stage32(DeviceMesh &dm, const double *X, StageArgs st, double *o, dou
 
 // 1-D operator tables of degree p (computed in long double, rounded to double).
 Ops1D basis_ops(int p);
+SgsOps sgs_ops(int p);
+
+// Records msg as the thread's last error and returns code (fr_last_error).
+int fr_fail(int code, const std::string &msg);
+
+// The closure network (fr_mlp.hip): its input count, and nu[s] = nu_scale * model(X[s]) for
+// s < n, enqueued on `stream`.
+int mlp_n_in(fr_mlp_s *m);
+int mlp_forward_nu(fr_mlp_s *m, const float *X, int64_t n, int64_t ldx, double *nu, double nu_scale,
+                   void *stream);
 
 // Returns "" on success or a message naming the offending element / face.
 std::string build_host_mesh(int p, int q, int64_t E, const int64_t *elem_vert, const double *elem_nodes,

@@ -1,21 +1,22 @@
-// fr_kernels.hip -- gfx950 kernels of the FR residual and RK stage, and the C ABI of libfr.
+// fr_kernels.hip -- gfx950 kernels of the FR residual and RK stage (FP64 operator path), and
+// the C ABI of libfr.
 //
-// One RK stage is two kernels over elements (section "FR Algorithm", Eq. (3)):
+// One RK stage is three kernels (section "FR Algorithm", Eq. (3)):
 //
-//   K1 "pre-pass"  per element: the solution and the broken physical gradient
-//                  G = |J|^-1 sum_n Ja^n d_n U interpolated to the element's own face points,
-//                  written once to an element-major face buffer [E][6][20][Nfp].
-//   K3 "element"   per element: recomputes its own face values, reads the neighbours' from
-//                  the face buffer, forms the common state, the BR2 common gradient and the
-//                  common normal flux (Rusanov or Roe inviscid part minus the viscous part) at
-//                  every face point, then the corrected gradient, the pointwise flux, its
-//                  transformed divergence plus the g_DG flux correction, R = -div/|J|, and the
-//                  RK register update -- all without writing anything else to memory.
+//   k_prepass  per element: the solution and the broken physical gradient
+//              G = |J|^-1 sum_n Ja^n d_n U interpolated to the element's own face points,
+//              written once to an element-major face buffer [E][6][20][Nfp];
+//   k_face     per face point: the common state, the BR2 common gradient and the common
+//              normal flux (Rusanov or Roe inviscid part minus the viscous part), computed once
+//              and written face-major with the jump (U_R - U_L)/2;
+//   k_volume   per element: the corrected gradient, the pointwise flux, its transformed
+//              divergence plus the g_DG flux correction, R = -div/|J|, and the RK register
+//              update.
 //
-// Each face's common flux is computed by both elements that share it, from the same inputs in
-// the same order (the owner side acts as "left"), so the two values are bitwise opposite and
-// the scheme stays exactly conservative. The element's data move through LDS; threads map to
-// solution points for volume work and to face points for interface work.
+// Both sides of a face read the same owner-side common flux, so the scheme is exactly
+// conservative. Element data move through LDS; threads map to solution points for volume work
+// and to face points for interface work. With the learned closure attached, each stage first
+// computes the per-element features (k_sgs_features) and the network's eddy viscosity.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -110,10 +111,11 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void 
 // Writes J = (U_R - U_L)/2 = U^C - U_L and the owner's transformed common normal flux
 // F^{I,perp}_L = |N| (F*_inv - F_v(U^C, G^I) . n) to a face-major buffer [F][10][Nfp].
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC>
+template <int P, typename real, bool VISC, bool SGS>
 __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
                                               const FaceRec *__restrict__ ftab, int64_t F, Phys<real> ph,
-                                              int flux, real *__restrict__ fout) {
+                                              int flux, real *__restrict__ fout, const double *__restrict__ nut,
+                                              real kt) {
   constexpr int N = P + 1, NFP = N * N;
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t fc = gid / NFP;
@@ -153,7 +155,14 @@ __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
         GI[i][v] = real(0.5) * (srcL[(5 + i * 5 + v) * NFP] + srcR[(5 + i * 5 + v) * NFP]) +
                    sig * NL[i] * (UR[v] - UL[v]);
     real Fv[3][5];
-    visc_flux(UC, GI, ph, Fv);
+    real mu = ph.mu, kap = ph.kappa;
+    if (SGS) {
+      // eddy viscosity: mean of the two elements' nu_t, density of the common state
+      const real mut = UC[0] * real(0.5 * (nut[r.eL] + nut[r.eR]));
+      mu += mut;
+      kap += mut * kt;
+    }
+    visc_flux_mk(UC, GI, ph.gm1, mu, kap, Fv);
 #pragma unroll
     for (int v = 0; v < 5; ++v) Fvn[v] = Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
   }
@@ -174,11 +183,12 @@ __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 // transformed divergence sum_n D_n F^n plus the flux correction
 // (s F^{I,perp} - F^d_f) g'(xi_d), R = -div/|J|, and the RK register update.
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC>
+template <int P, typename real, bool VISC, bool SGS>
 __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k_volume(
     const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
-    double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2) {
+    double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2,
+    const double *__restrict__ nut, real kt) {
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
   constexpr int NJ = (VISC ? 10 : 5) * NF;
@@ -283,7 +293,13 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k
           G[i][v] = iJ * g;
         }
       real Fv[3][5];
-      visc_flux(U, G, ph, Fv);
+      real mu = ph.mu, kap = ph.kappa;
+      if (SGS) {
+        const real mut = U[0] * real(nut[e]);
+        mu += mut;
+        kap += mut * kt;
+      }
+      visc_flux_mk(U, G, ph.gm1, mu, kap, Fv);
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -384,6 +400,132 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Inputs of the learned closure per element (fr_sgs_features in fr.h): modal energies of the
+// velocity polynomial u = m/rho (tensor projection on orthonormal Legendre modes, one
+// direction at a time through LDS) and five volume-averaged invariants of its broken gradient
+// (a fixed-order tree reduction over the element's points). FP64, rounded to float once.
+// ------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_sgs_features(const double *__restrict__ X,
+                                                                 const double *__restrict__ geo, int64_t E,
+                                                                 OpsT<double> ops, SgsOps so,
+                                                                 float *__restrict__ feat) {
+  using C = Cfg<P>;
+  constexpr int N = C::N, NS = C::NS, EPB = C::EPB, NFT = NS + 4;
+  constexpr int P2 = NS <= 1 ? 1 : (NS <= 2 ? 2 : (NS <= 4 ? 4 : (NS <= 8 ? 8 : (NS <= 16 ? 16 : (NS <= 32 ? 32 :
+                     (NS <= 64 ? 64 : (NS <= 128 ? 128 : (NS <= 256 ? 256 : 512))))))));
+  __shared__ double sA[EPB][3][NS];
+  __shared__ double sB[EPB][3][NS];
+  __shared__ double sR[EPB][6][NS];
+  const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const bool act = e < E;
+  const int idx[3] = {t % N, (t / N) % N, t / (N * N)};
+  double ja[9], iJ = 1.0;
+  if (act) {
+    const double rho = X[(e * 5) * NS + t];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sA[slot][j][t] = X[(e * 5 + 1 + j) * NS + t] / rho;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
+    iJ = geo[(e * 10 + 9) * NS + t];
+  }
+  __syncthreads();
+  double q[6] = {0, 0, 0, 0, 0, 0};
+  if (act) {
+    double du[3][3];  // du[d][j] = d u_j / d xi_d
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        d0 += ops.D[idx[0] * N + c] * sA[slot][j][c + N * (idx[1] + N * idx[2])];
+        d1 += ops.D[idx[1] * N + c] * sA[slot][j][idx[0] + N * (c + N * idx[2])];
+        d2 += ops.D[idx[2] * N + c] * sA[slot][j][idx[0] + N * (idx[1] + N * c)];
+      }
+      du[0][j] = d0;
+      du[1][j] = d1;
+      du[2][j] = d2;
+    }
+    double A[3][3];  // A[i][j] = d u_j / d x_i
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[i][j] = iJ * (ja[i] * du[0][j] + ja[3 + i] * du[1][j] + ja[6 + i] * du[2][j]);
+    double ss = 0, ww = 0, t3 = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double S = 0.5 * (A[i][j] + A[j][i]), W = 0.5 * (A[i][j] - A[j][i]);
+        ss += S * S;
+        ww += W * W;
+        t3 += A[i][j] * (A[j][0] * A[0][i] + A[j][1] * A[1][i] + A[j][2] * A[2][i]);
+      }
+    const double tr = A[0][0] + A[1][1] + A[2][2];
+    const double wq = so.w[idx[0]] * so.w[idx[1]] * so.w[idx[2]] / iJ;
+    q[0] = wq;
+    q[1] = wq * 2 * ss;
+    q[2] = wq * 2 * ww;
+    q[3] = wq * (-t3 / 3);
+    q[4] = wq * tr;
+    q[5] = wq * tr * tr;
+    // modal projection along xi
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += so.Lm[idx[0] * N + c] * sA[slot][j][c + N * (idx[1] + N * idx[2])];
+      sB[slot][j][t] = acc;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sR[slot][k][t] = q[k];
+  __syncthreads();
+  if (act) {  // along eta
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += so.Lm[idx[1] * N + c] * sB[slot][j][idx[0] + N * (c + N * idx[2])];
+      sA[slot][j][t] = acc;
+    }
+  }
+  __syncthreads();
+  if (act) {  // along zeta; thread t now owns mode t
+    double ek = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += so.Lm[idx[2] * N + c] * sA[slot][j][idx[0] + N * (idx[1] + N * c)];
+      ek += acc * acc;
+    }
+    if (t > 0) feat[e * NFT + t - 1] = (float)log(ek / 16 + 1e-12);
+  }
+#pragma unroll
+  for (int h = P2 / 2; h > 0; h >>= 1) {
+    if (t < h && t + h < NS) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sR[slot][k][t] += sR[slot][k][t + h];
+    }
+    __syncthreads();
+  }
+  if (act && t == 0) {
+    const double vol = sR[slot][0][0];
+    const double s2 = sR[slot][1][0] / vol, w2 = sR[slot][2][0] / vol, r = sR[slot][3][0] / vol;
+    const double th = sR[slot][4][0] / vol, th2 = sR[slot][5][0] / vol;
+    const double eps = 1e-12;
+    float *o = feat + e * NFT + NS - 1;
+    o[0] = (float)(0.5 * log(s2 + eps));
+    o[1] = (float)(0.5 * log(w2 + eps));
+    o[2] = (float)(r / pow(s2 + eps, 1.5));
+    o[3] = (float)(th / sqrt(s2 + eps));
+    o[4] = (float)(th2 / (s2 + eps));
+  }
+}
+
 // Per-block partial sums of w|J| (1), w|J| |m|^2/(2 rho) (2) and w|J| (u.R_m - |u|^2 R_rho/2)
 // (3); one block per 256 solution points, fixed reduction order.
 __global__ __launch_bounds__(256) void k_kinetic(const double *__restrict__ U, const double *__restrict__ R,
@@ -443,6 +585,8 @@ static int fail(int code, const std::string &msg) {
   return code;
 }
 
+int frk::fr_fail(int code, const std::string &msg) { return fail(code, msg); }
+
 #define HIPCHK(call)                                                                    \
   do {                                                                                  \
     hipError_t e_ = (call);                                                             \
@@ -452,7 +596,33 @@ static int fail(int code, const std::string &msg) {
 static bool valid(fr_mesh_t m) { return m != nullptr && m->magic == kMagic; }
 
 // ms (optional): accumulates the durations of the three kernels, measured with HIP events.
-template <int P, typename real, bool VISC>
+template <int P>
+static int launch_features(DeviceMesh &dm, const double *X, float *feat) {
+  using C = Cfg<P>;
+  OpsT<double> ops;
+  std::memcpy(ops.D, dm.ops.D, sizeof ops.D);
+  const int64_t blocks = (dm.E + C::EPB - 1) / C::EPB;
+  hipLaunchKernelGGL((k_sgs_features<P>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, (hipStream_t)dm.stream, X,
+                     (const double *)dm.geo, dm.E, ops, dm.sgs_ops, feat);
+  HIPCHK(hipGetLastError());
+  return FR_OK;
+}
+
+static int features(DeviceMesh &dm, const double *X, float *feat) {
+  switch (dm.p) {
+    case 0: return launch_features<0>(dm, X, feat);
+    case 1: return launch_features<1>(dm, X, feat);
+    case 2: return launch_features<2>(dm, X, feat);
+    case 3: return launch_features<3>(dm, X, feat);
+    case 4: return launch_features<4>(dm, X, feat);
+    case 5: return launch_features<5>(dm, X, feat);
+    case 6: return launch_features<6>(dm, X, feat);
+    case 7: return launch_features<7>(dm, X, feat);
+    default: return fail(FR_ERR_UNSUPPORTED, "p out of range");
+  }
+}
+
+template <int P, typename real, bool VISC, bool SGS>
 static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
                           double *ms) {
   using C = Cfg<P>;
@@ -465,6 +635,8 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
     ops.gcR[i] = real(dm.ops.gcR[i]);
   }
   Phys<real> ph{real(dm.phys.gamma), real(dm.phys.gamma - 1.0), real(dm.phys.mu), real(dm.phys.kappa)};
+  // heat-flux coefficient per unit eddy viscosity: gamma / ((gamma - 1) Pr_t)
+  const real kt = real(dm.phys.gamma / ((dm.phys.gamma - 1.0) * dm.prandtl_t));
   const int64_t blocks = (dm.E + C::EPB - 1) / C::EPB;
   const int64_t fblocks = (dm.F * C::NFP + 255) / 256;
   hipStream_t s = (hipStream_t)dm.stream;
@@ -477,12 +649,13 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
                      (const real *)dm.geo, (real *)dm.face, dm.E, ops);
   HIPCHK(hipGetLastError());
   if (ms) HIPCHK(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL((k_face<P, real, VISC>), dim3((unsigned)fblocks), dim3(256), 0, s, (const real *)dm.face,
-                     (const real *)dm.fgeo, dm.ftab, dm.F, ph, dm.flux, (real *)dm.fout);
+  hipLaunchKernelGGL((k_face<P, real, VISC, SGS>), dim3((unsigned)fblocks), dim3(256), 0, s, (const real *)dm.face,
+                     (const real *)dm.fgeo, dm.ftab, dm.F, ph, dm.flux, (real *)dm.fout, dm.nut, kt);
   HIPCHK(hipGetLastError());
   if (ms) HIPCHK(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL((k_volume<P, real, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
-                     (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1, reg2);
+  hipLaunchKernelGGL((k_volume<P, real, VISC, SGS>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+                     (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1, reg2,
+                     dm.nut, kt);
   HIPCHK(hipGetLastError());
   if (ms) {
     HIPCHK(hipEventRecord(ev[3], s));
@@ -497,18 +670,18 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
   return FR_OK;
 }
 
-template <typename real, bool VISC>
+template <typename real, bool VISC, bool SGS>
 static int launch_stage_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
                           double *ms) {
   switch (dm.p) {
-    case 0: return launch_stage_t<0, real, VISC>(dm, X, st, o, r1, r2, ms);
-    case 1: return launch_stage_t<1, real, VISC>(dm, X, st, o, r1, r2, ms);
-    case 2: return launch_stage_t<2, real, VISC>(dm, X, st, o, r1, r2, ms);
-    case 3: return launch_stage_t<3, real, VISC>(dm, X, st, o, r1, r2, ms);
-    case 4: return launch_stage_t<4, real, VISC>(dm, X, st, o, r1, r2, ms);
-    case 5: return launch_stage_t<5, real, VISC>(dm, X, st, o, r1, r2, ms);
-    case 6: return launch_stage_t<6, real, VISC>(dm, X, st, o, r1, r2, ms);
-    case 7: return launch_stage_t<7, real, VISC>(dm, X, st, o, r1, r2, ms);
+    case 0: return launch_stage_t<0, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 1: return launch_stage_t<1, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 2: return launch_stage_t<2, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 3: return launch_stage_t<3, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 4: return launch_stage_t<4, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 5: return launch_stage_t<5, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 6: return launch_stage_t<6, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 7: return launch_stage_t<7, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
     default: return fail(FR_ERR_UNSUPPORTED, "p out of range");
   }
 }
@@ -520,8 +693,18 @@ static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o
     int rc = launch_stage32(dm, X, st, o, r1, r2, ms, err);
     return rc ? fail(rc, err) : FR_OK;
   }
-  return dm.viscous ? launch_stage_p<double, true>(dm, X, st, o, r1, r2, ms)
-                    : launch_stage_p<double, false>(dm, X, st, o, r1, r2, ms);
+  if (dm.sgs) {
+    if (dm.sgs == 2) {
+      // the closure's eddy viscosity of the state this stage is evaluated on
+      int rc = features(dm, X, dm.feat);
+      if (rc) return rc;
+      rc = mlp_forward_nu(dm.model, dm.feat, dm.E, dm.Ns + 4, dm.nut, dm.nu_scale, dm.stream);
+      if (rc) return rc;
+    }
+    return launch_stage_p<double, true, true>(dm, X, st, o, r1, r2, ms);
+  }
+  return dm.viscous ? launch_stage_p<double, true, false>(dm, X, st, o, r1, r2, ms)
+                    : launch_stage_p<double, false, false>(dm, X, st, o, r1, r2, ms);
 }
 
 // Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients.
@@ -620,6 +803,7 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   dm.eta = d->br2_eta;
   dm.phys = Physics{d->gamma, d->prandtl, d->mu, d->mu * d->gamma / (d->prandtl * (d->gamma - 1.0))};
   dm.ops = H.ops;
+  dm.sgs_ops = sgs_ops(d->p);
   dm.stream = hip_stream;
   m->xyz = std::move(H.xyz);
   (void)hipGetDevice(&m->device);
@@ -716,7 +900,8 @@ int fr_mesh_destroy(fr_mesh_t m) {
   if (dm.stream) (void)hipStreamSynchronize((hipStream_t)dm.stream);
   else (void)hipDeviceSynchronize();
   void *bufs[] = {dm.U,     dm.R1,    dm.R2,    dm.geo,    dm.fgeo,  dm.ftab,  dm.fref, dm.face,
-                  dm.fout,  dm.geo32, dm.face32, dm.facem, dm.fout32, dm.foutm, dm.flag};
+                  dm.fout,  dm.geo32, dm.face32, dm.facem, dm.fout32, dm.foutm, dm.flag, dm.nut,
+                  dm.feat};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   m->magic = 0;
@@ -849,6 +1034,85 @@ int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_b
   if (n_elem) *n_elem = m->dm.E;
   if (n_sol) *n_sol = m->dm.Ns;
   if (device_bytes) *device_bytes = m->dm.bytes;
+  return FR_OK;
+}
+
+int fr_sgs_n_features(int p) {
+  if (p < 0 || p > kMaxP) return fail(FR_ERR_ARG, "p must be in 0..7");
+  return (p + 1) * (p + 1) * (p + 1) + 4;
+}
+
+int fr_sgs_features(fr_mesh_t m, float *feat) {
+  if (!valid(m) || !feat) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  if (m->dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "the closure needs prec = FR_FP64");
+  return features(m->dm, m->dm.U, feat);
+}
+
+static int ensure_nut(DeviceMesh &dm) {
+  if (!dm.nut) {
+    HIPCHK(hipMalloc(&dm.nut, dm.E * sizeof(double)));
+    dm.bytes += dm.E * sizeof(double);
+  }
+  return FR_OK;
+}
+
+int fr_set_eddy_viscosity(fr_mesh_t m, const double *nu, int on_device, double prandtl_t) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  DeviceMesh &dm = m->dm;
+  if (dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "the closure needs prec = FR_FP64");
+  if (!nu) {
+    dm.sgs = 0;
+    dm.model = nullptr;
+    return FR_OK;
+  }
+  if (!(prandtl_t > 0.0)) return fail(FR_ERR_ARG, "prandtl_t must be > 0");
+  if (!on_device) {
+    for (int64_t e = 0; e < dm.E; ++e)
+      if (!(nu[e] >= 0.0) || !std::isfinite(nu[e])) return fail(FR_ERR_ARG, "eddy viscosity must be finite and >= 0");
+  }
+  int rc = ensure_nut(dm);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)dm.stream;
+  HIPCHK(hipMemcpyAsync(dm.nut, nu, dm.E * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        s));
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));
+  dm.sgs = 1;
+  dm.model = nullptr;
+  dm.prandtl_t = prandtl_t;
+  return FR_OK;
+}
+
+int fr_set_sgs_model(fr_mesh_t m, fr_mlp_t model, double nu_scale, double prandtl_t) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  DeviceMesh &dm = m->dm;
+  if (dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "the closure needs prec = FR_FP64");
+  if (!model) {
+    dm.sgs = 0;
+    dm.model = nullptr;
+    return FR_OK;
+  }
+  if (mlp_n_in(model) != dm.Ns + 4) return fail(FR_ERR_ARG, "the model's n_in must be (p+1)^3 + 4");
+  if (!(prandtl_t > 0.0) || !(nu_scale >= 0.0)) return fail(FR_ERR_ARG, "need prandtl_t > 0 and nu_scale >= 0");
+  int rc = ensure_nut(dm);
+  if (rc) return rc;
+  if (!dm.feat) {
+    HIPCHK(hipMalloc(&dm.feat, dm.E * (dm.Ns + 4) * sizeof(float)));
+    dm.bytes += dm.E * (dm.Ns + 4) * sizeof(float);
+  }
+  dm.sgs = 2;
+  dm.model = model;
+  dm.nu_scale = nu_scale;
+  dm.prandtl_t = prandtl_t;
+  return FR_OK;
+}
+
+int fr_get_eddy_viscosity(fr_mesh_t m, double *nu) {
+  if (!valid(m) || !nu) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  DeviceMesh &dm = m->dm;
+  if (!dm.nut) return fail(FR_ERR_ARG, "no eddy viscosity has been set or computed");
+  hipStream_t s = (hipStream_t)dm.stream;
+  HIPCHK(hipMemcpyAsync(nu, dm.nut, dm.E * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   return FR_OK;
 }
 

@@ -67,9 +67,30 @@ def load():
     L.fr_mesh_geometry_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, P, P, P, P]
     L.fr_basis_host.argtypes = [i32, P, P, P, P, P]
     L.fr_kinetic_energy.argtypes = [P, P]
+    # learned eddy-viscosity closure
+    L.fr_sgs_n_features.argtypes = [i32]
+    L.fr_sgs_features.argtypes = [P, P]
+    L.fr_set_eddy_viscosity.argtypes = [P, P, i32, f64]
+    L.fr_set_sgs_model.argtypes = [P, P, f64, f64]
+    L.fr_get_eddy_viscosity.argtypes = [P, P]
+    L.fr_mlp_n_params.argtypes = [ctypes.c_int32]
+    L.fr_mlp_n_params.restype = i64
+    L.fr_mlp_create.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.POINTER(P)]
+    L.fr_mlp_destroy.argtypes = [P]
+    L.fr_mlp_set_stream.argtypes = [P, P]
+    L.fr_mlp_set_params.argtypes = [P, P]
+    L.fr_mlp_get_params.argtypes = [P, P]
+    L.fr_mlp_get_bf16.argtypes = [P, P, P, P]
+    L.fr_mlp_forward.argtypes = [P, P, i64, i64, P]
+    L.fr_mlp_loss_grad.argtypes = [P, P, i64, i64, P, P, ctypes.POINTER(f64)]
+    L.fr_mlp_train_step.argtypes = [P, P, i64, i64, P, ctypes.c_float, P]
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
-                 "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy"):
+                 "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy", "fr_sgs_n_features",
+                 "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
+                 "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
+                 "fr_mlp_get_params", "fr_mlp_get_bf16", "fr_mlp_forward", "fr_mlp_loss_grad",
+                 "fr_mlp_train_step"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -203,7 +224,134 @@ class FRMesh:
         _check(load().fr_kinetic_energy(self.h, out.ctypes.data))
         return float(out[0]), float(out[1])
 
+    # ---- learned eddy-viscosity closure ----
+    @property
+    def n_features(self) -> int:
+        return self.Ns + 4
+
+    def sgs_features(self, out=None):
+        """Closure inputs of the current state (fr_sgs_features) into a float32 device tensor
+        [E][Ns + 4] (allocated with torch if `out` is None)."""
+        import torch
+
+        if out is None:
+            out = torch.empty((self.E, self.n_features), dtype=torch.float32, device="cuda")
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (self.E, self.n_features)
+        _check(load().fr_sgs_features(self.h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def set_eddy_viscosity(self, nu, prandtl_t: float = 0.9):
+        """Fixed per-element nu_t [E] (numpy, or a float64 device tensor), or None to switch off."""
+        if nu is None:
+            _check(load().fr_set_eddy_viscosity(self.h, None, 0, prandtl_t))
+        elif hasattr(nu, "data_ptr"):
+            assert nu.is_cuda and nu.is_contiguous() and tuple(nu.shape) == (self.E,)
+            _check(load().fr_set_eddy_viscosity(self.h, ctypes.c_void_p(nu.data_ptr()), 1, prandtl_t))
+        else:
+            nu = np.ascontiguousarray(nu, dtype=np.float64)
+            assert nu.shape == (self.E,)
+            _check(load().fr_set_eddy_viscosity(self.h, nu.ctypes.data, 0, prandtl_t))
+
+    def set_sgs_model(self, model, nu_scale: float = 0.0, prandtl_t: float = 0.9):
+        """Attach an MLP (nu_t = nu_scale * model(features) per stage), or None to detach."""
+        self._model = model  # kept alive while attached
+        _check(load().fr_set_sgs_model(self.h, model.h if model is not None else None, float(nu_scale),
+                                       float(prandtl_t)))
+
+    def eddy_viscosity(self) -> np.ndarray:
+        nu = np.empty(self.E)
+        _check(load().fr_get_eddy_viscosity(self.h, nu.ctypes.data))
+        return nu
+
     def info(self):
         E, ns, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
         _check(load().fr_mesh_info(self.h, ctypes.byref(E), ctypes.byref(ns), ctypes.byref(b)))
         return {"n_elem": E.value, "n_sol": ns.value, "device_bytes": b.value}
+
+
+H = 64
+
+
+def mlp_n_params(n_in: int) -> int:
+    return int(load().fr_mlp_n_params(int(n_in)))
+
+
+class MLP:
+    """The closure network on the current GPU (fr_mlp_*). Parameters are float32 numpy arrays in
+    the layout W1[64][n_in], b1[64], W2[64][64], b2[64], w3[64], b3[1]; inputs and targets are
+    float32 device tensors."""
+
+    def __init__(self, n_in: int, params, mean, std, stream=None):
+        L = load()
+        self.n_in = int(n_in)
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        mean = np.ascontiguousarray(mean, dtype=np.float32)
+        std = np.ascontiguousarray(std, dtype=np.float32)
+        assert params.shape == (mlp_n_params(n_in),) and mean.shape == (n_in,) and std.shape == (n_in,)
+        self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        h = ctypes.c_void_p()
+        _check(L.fr_mlp_create(self.n_in, params.ctypes.data, mean.ctypes.data, std.ctypes.data, self._stream,
+                               ctypes.byref(h)))
+        self.h = h
+        self.n_params = params.size
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().fr_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        assert params.shape == (self.n_params,)
+        _check(load().fr_mlp_set_params(self.h, params.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(load().fr_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def get_bf16(self):
+        W1 = np.empty((H, self.n_in), dtype=np.uint16)
+        W2 = np.empty((H, H), dtype=np.uint16)
+        w3 = np.empty(H, dtype=np.uint16)
+        _check(load().fr_mlp_get_bf16(self.h, W1.ctypes.data, W2.ctypes.data, w3.ctypes.data))
+        return W1, W2, w3
+
+    @staticmethod
+    def _x(X):
+        assert X.is_cuda and X.dtype.is_floating_point and X.element_size() == 4 and X.dim() == 2
+        assert X.stride(1) == 1
+        return ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), int(X.stride(0))
+
+    def forward(self, X, out=None):
+        import torch
+
+        xp, n, ld = self._x(X)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=X.device)
+        _check(load().fr_mlp_forward(self.h, xp, n, ld, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def loss_grad(self, X, t):
+        """(loss, gradient [n_params] float32 numpy) without updating."""
+        xp, n, ld = self._x(X)
+        assert t.is_cuda and t.is_contiguous() and t.numel() == n and t.element_size() == 4
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(load().fr_mlp_loss_grad(self.h, xp, n, ld, ctypes.c_void_p(t.data_ptr()), g.ctypes.data,
+                                       ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, t, lr: float, loss_out=None):
+        """One Adam step; loss_out (float32 device tensor of one element) receives the loss."""
+        xp, n, ld = self._x(X)
+        assert t.is_cuda and t.is_contiguous() and t.numel() == n and t.element_size() == 4
+        lp = ctypes.c_void_p(loss_out.data_ptr()) if loss_out is not None else None
+        _check(load().fr_mlp_train_step(self.h, xp, n, ld, ctypes.c_void_p(t.data_ptr()), float(lr), lp))
