@@ -19,7 +19,7 @@ SRC = os.path.join(_HERE, "fr_oracle.cpp")
 
 PREC = {"f64": 0, "ld": 1, "f32": 2}
 FLUX = {"rusanov": 0, "roe": 1}
-SCHEME = {"rk4": 0, "lsrk45": 1}
+SCHEME = {"rk4": 0, "lsrk45": 1, "ssprk104": 2}
 
 _lib = None
 
@@ -58,9 +58,11 @@ def _load():
     L.ora_inviscid_flux.argtypes = [f64, P, P, P]
     L.ora_viscous_flux.argtypes = [f64, f64, f64, P, P, P]
     L.ora_rk_scalar.argtypes = [i32, i32, f64, f64, f64, i32, P]
+    L.ora_rk_upwind.argtypes = [i32, i32, f64, i32, P]
     L.ora_n_features.argtypes = [P]
     L.ora_sgs_features.argtypes = [P, P, P]
     L.ora_set_eddy_viscosity.argtypes = [P, P, f64]
+    L.ora_set_body_force.argtypes = [P, P]
     _lib = L
     return L
 
@@ -144,6 +146,12 @@ class Oracle:
         if rc:
             raise RuntimeError("oracle: " + _load().ora_last_error().decode())
 
+    def set_body_force(self, g):
+        """Constant body force per unit mass (3 values) for every later residual."""
+        self._g = np.ascontiguousarray(g, dtype=np.float64)
+        assert self._g.shape == (3,)
+        _load().ora_set_body_force(self.h, _ptr(self._g))
+
     def sgs_features(self, U: np.ndarray) -> np.ndarray:
         """Inputs of the learned closure per (active) element: [NA][(p+1)^3 + 4]."""
         U = np.ascontiguousarray(U, dtype=np.float64)
@@ -218,3 +226,12 @@ def rk_scalar(scheme: str, ode: int, lam: float, y0: float, dt: float, nsteps: i
     out = np.empty(nsteps + 1)
     _load().ora_rk_scalar(SCHEME[scheme], ode, lam, y0, dt, nsteps, _ptr(out))
     return out
+
+
+def rk_upwind(scheme: str, u0, dt: float, nsteps: int) -> np.ndarray:
+    """The RK driver on periodic first-order upwind advection with unit spacing."""
+    u = np.array(u0, dtype=np.float64, order="C", copy=True)
+    rc = _load().ora_rk_upwind(SCHEME[scheme], u.size, dt, nsteps, _ptr(u))
+    if rc:
+        raise RuntimeError("oracle rk_upwind failed")
+    return u

@@ -426,6 +426,23 @@ int rk_advance(vector<T> &U, T dt, int scheme, int nsteps,
           U[i] = U[i] + Bc[st] * dU[i];
         }
       }
+    } else if (scheme == 2) {
+      // Ketcheson's ten-stage, fourth-order strong-stability-preserving method (SSP
+      // coefficient 6) in its two-register form: five forward-Euler stages of dt/6, a
+      // combination of the two registers, four more stages, and a final combined stage
+      vector<T> q1 = U, q2 = U;
+      auto euler_stage = [&]() {
+        resid(q1, R);
+        for (size_t i = 0; i < M; ++i) q1[i] = q1[i] + dt / 6 * R[i];
+      };
+      for (int st = 0; st < 5; ++st) euler_stage();
+      for (size_t i = 0; i < M; ++i) {
+        q2[i] = q2[i] / 25 + T(9) / 25 * q1[i];
+        q1[i] = 15 * q2[i] - 5 * q1[i];
+      }
+      for (int st = 0; st < 4; ++st) euler_stage();
+      resid(q1, R);
+      for (size_t i = 0; i < M; ++i) U[i] = q2[i] + T(3) / 5 * q1[i] + dt / 10 * R[i];
     } else {
       return -1;
     }
@@ -444,6 +461,7 @@ struct Iface {
   virtual int n_features() const = 0;
   virtual int set_eddy_viscosity(const double *nu, double prandtl_t) = 0;
   virtual std::string last_err() const = 0;
+  virtual void set_body_force(const double *g) = 0;
 };
 
 template <class T>
@@ -469,6 +487,7 @@ struct Oracle : Iface {
   vector<T> Jf;    // [slot][6][Nfp]    |J| interpolated to face points
   vector<T> Xs;    // [slot][3][Ns]     solution point coordinates
   int nthreads;
+  T force[3] = {0, 0, 0};  // body force per unit mass (the source term S of Eq. (3))
   vector<T> nut;          // [E] eddy kinematic viscosity per element; empty = none
   T prandtl_t = T(0.9);   // turbulent Prandtl number
 
@@ -487,6 +506,9 @@ struct Oracle : Iface {
 
   std::string err;
   std::string last_err() const override { return err; }
+  void set_body_force(const double *g) override {
+    for (int i = 0; i < 3; ++i) force[i] = T(g[i]);
+  }
 
   // rounding of a long-double metric term to T, optionally moved by one unit in the last place
   T round_geo(long double v, uint64_t key) const {
@@ -938,6 +960,18 @@ struct Oracle : Iface {
       }
       for (int v = 0; v < 5; ++v)
         for (int s = 0; s < Ns; ++s) R[(ia * 5 + v) * Ns + s] = -div[v * Ns + s] / detJ[sl * Ns + s];
+      // source term S of Eq. (3): a body force g per unit mass adds rho g to the momentum and
+      // the work m . g to the energy
+      if (force[0] != T(0) || force[1] != T(0) || force[2] != T(0)) {
+        for (int s = 0; s < Ns; ++s) {
+          T work = 0;
+          for (int i = 0; i < 3; ++i) {
+            R[(ia * 5 + 1 + i) * Ns + s] += U[s] * force[i];
+            work += U[(1 + i) * Ns + s] * force[i];
+          }
+          R[(ia * 5 + 4) * Ns + s] += work;
+        }
+      }
     }
     return 0;
   }
@@ -1145,6 +1179,12 @@ void ora_destroy(void *h) { delete static_cast<Iface *>(h); }
 
 int ora_n_features(void *h) { return static_cast<Iface *>(h)->n_features(); }
 
+// body force per unit mass g[3] (the source term of Eq. (3)); zero switches it off
+int ora_set_body_force(void *h, const double *g) {
+  static_cast<Iface *>(h)->set_body_force(g);
+  return 0;
+}
+
 // feat: [n_active][n_features] doubles
 int ora_sgs_features(void *h, const double *U, double *feat) { return static_cast<Iface *>(h)->sgs_features(U, feat); }
 
@@ -1221,6 +1261,18 @@ int ora_viscous_flux(double gamma, double prandtl, double mu, const double *U, c
 
 // The same RK drivers applied to a scalar ODE (ode 0: y' = lam*y; ode 1: y' = -y^2), so the
 // time integrators can be pinned by their convergence order. out[nsteps+1] holds y_0..y_n.
+// The Runge-Kutta driver on first-order upwind advection u_j' = u_{j-1} - u_j on a periodic
+// grid of n cells (unit spacing; forward Euler keeps it monotone for dt <= 1): u [n] is
+// advanced in place by nsteps steps of size dt.
+int ora_rk_upwind(int scheme, int n, double dt, int nsteps, double *u) {
+  vector<double> y(u, u + n);
+  int rc = rk_advance<double>(y, dt, scheme, nsteps, [&](const vector<double> &Y, vector<double> &R) {
+    for (int j = 0; j < n; ++j) R[j] = Y[(j + n - 1) % n] - Y[j];
+  });
+  for (int j = 0; j < n; ++j) u[j] = y[j];
+  return rc;
+}
+
 int ora_rk_scalar(int scheme, int ode, double lam, double y0, double dt, int nsteps, double *out) {
   vector<double> y(1, y0);
   out[0] = y0;
