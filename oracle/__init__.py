@@ -63,6 +63,7 @@ def _load():
     L.ora_sgs_features.argtypes = [P, P, P]
     L.ora_set_eddy_viscosity.argtypes = [P, P, f64]
     L.ora_set_body_force.argtypes = [P, P]
+    L.ora_set_viscous_scheme.argtypes = [P, i32, f64]
     _lib = L
     return L
 
@@ -143,6 +144,12 @@ class Oracle:
             self._nut = np.ascontiguousarray(nu_t, dtype=np.float64)
             assert self._nut.shape == (self.E,)
             rc = _load().ora_set_eddy_viscosity(self.h, _ptr(self._nut), prandtl_t)
+        if rc:
+            raise RuntimeError("oracle: " + _load().ora_last_error().decode())
+
+    def set_viscous_scheme(self, scheme: str = "br2", tau: float = 0.1):
+        """"br2" (default) or "ldg" with penalty tau (LDG needs the full mesh)."""
+        rc = _load().ora_set_viscous_scheme(self.h, {"br2": 0, "ldg": 1}[scheme], tau)
         if rc:
             raise RuntimeError("oracle: " + _load().ora_last_error().decode())
 

@@ -462,6 +462,7 @@ struct Iface {
   virtual int set_eddy_viscosity(const double *nu, double prandtl_t) = 0;
   virtual std::string last_err() const = 0;
   virtual void set_body_force(const double *g) = 0;
+  virtual int set_viscous_scheme(int scheme, double tau) = 0;
 };
 
 template <class T>
@@ -488,6 +489,8 @@ struct Oracle : Iface {
   vector<T> Xs;    // [slot][3][Ns]     solution point coordinates
   int nthreads;
   T force[3] = {0, 0, 0};  // body force per unit mass (the source term S of Eq. (3))
+  int visc_scheme = 0;     // 0 BR2, 1 LDG
+  T ldg_tau = T(0.1);      // LDG penalty on the jump of every conserved variable
   vector<T> nut;          // [E] eddy kinematic viscosity per element; empty = none
   T prandtl_t = T(0.9);   // turbulent Prandtl number
 
@@ -506,6 +509,13 @@ struct Oracle : Iface {
 
   std::string err;
   std::string last_err() const override { return err; }
+  int set_viscous_scheme(int scheme, double tau) override {
+    if (scheme != 0 && scheme != 1) { err = "unknown viscous scheme"; return -1; }
+    if (scheme == 1 && (int64_t)active.size() != E) { err = "LDG needs the full mesh"; return -1; }
+    visc_scheme = scheme;
+    ldg_tau = T(tau);
+    return 0;
+  }
   void set_body_force(const double *g) override {
     for (int i = 0; i < 3; ++i) force[i] = T(g[i]);
   }
@@ -828,6 +838,65 @@ struct Oracle : Iface {
           }
       }
     }
+    // pass 1b (LDG, section "FR Algorithm": the viscous flux by the local DG method): the
+    // common solution is one-sided, U^ = U_R (beta = +n_owner / 2), so each element's
+    // corrected gradient uses U^ - U_K = U_R - U_L on the faces it owns and 0 on the others;
+    // the corrected physical gradient is interpolated to the element's face points (it takes
+    // the place of the broken gradient in Gf)
+    const bool ldg = viscous && visc_scheme == 1;
+    if (ldg) {
+      vector<T> Gc(Gf.size());
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+      for (int64_t e = 0; e < E; ++e) {
+        const int64_t sl = slot[e];
+        const T *U = &Ufull[e * 5 * Ns];
+        vector<T> dU(3 * 5 * Ns);
+        for (int d = 0; d < 3; ++d)
+          for (int v = 0; v < 5; ++v) ref_deriv(d, U + v * Ns, &dU[(d * 5 + v) * Ns]);
+        for (int f = 0; f < 6; ++f) {
+          const FaceLink &lk = links[e * 6 + f];
+          if (!lk.owner) continue;  // U^ - U_K = 0 on faces this element does not own
+          int d = f / 2, sd = f % 2;
+          T sg = sd ? T(1) : T(-1);
+          const vector<T> &gc = sd ? B.gcR : B.gcL;
+          const int64_t sR = slot[lk.nbr];
+          for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+              int k = a + n * b;
+              for (int v = 0; v < 5; ++v) {
+                T jump = Uf[((sR * 6 + lk.nface) * Nfp + lk.perm[k]) * 5 + v] - Uf[((sl * 6 + f) * Nfp + k) * 5 + v];
+                for (int c = 0; c < n; ++c) dU[(d * 5 + v) * Ns + pt(d, c, a, b)] += sg * jump * gc[c];
+              }
+            }
+        }
+        vector<T> G(3 * 5 * Ns);
+        for (int s = 0; s < Ns; ++s) {
+          const T *ja = &Ja[(sl * Ns + s) * 9];
+          T iJ = T(1) / detJ[sl * Ns + s];
+          for (int i = 0; i < 3; ++i)
+            for (int v = 0; v < 5; ++v) {
+              T g = 0;
+              for (int d = 0; d < 3; ++d) g += ja[d * 3 + i] * dU[(d * 5 + v) * Ns + s];
+              G[(i * 5 + v) * Ns + s] = iJ * g;
+            }
+        }
+        for (int f = 0; f < 6; ++f) {
+          int d = f / 2, sd = f % 2;
+          const vector<T> &ell = sd ? B.lp : B.lm;
+          for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+              int k = a + n * b;
+              for (int i = 0; i < 3; ++i)
+                for (int v = 0; v < 5; ++v) {
+                  T sgv = 0;
+                  for (int c = 0; c < n; ++c) sgv += ell[c] * G[(i * 5 + v) * Ns + pt(d, c, a, b)];
+                  Gc[(((sl * 6 + f) * Nfp + k) * 3 + i) * 5 + v] = sgv;
+                }
+            }
+        }
+      }
+      Gf.swap(Gc);
+    }
     // pass 2: per face (owner side L), common state and transformed common normal flux
     const T cl = T(n) * T(n) / 2;  // g_R'(1) = (p+1)^2/2
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
@@ -849,12 +918,22 @@ struct Oracle : Iface {
           T nm = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
           T nh[3] = {N[0] / nm, N[1] / nm, N[2] / nm};
           T UC[5];
-          for (int v = 0; v < 5; ++v) UC[v] = T(0.5) * (UL[v] + UR[v]);
+          for (int v = 0; v < 5; ++v) UC[v] = ldg ? UR[v] : T(0.5) * (UL[v] + UR[v]);
           T Fi[5];
           if (flux == 0) rusanov<T>(UL, UR, nh, gas.gamma, Fi);
           else roe<T>(UL, UR, nh, gas.gamma, Fi);
           T Fvn[5] = {0, 0, 0, 0, 0};
-          if (viscous) {
+          if (ldg) {
+            // LDG: the owner's viscous flux with its corrected gradient, plus the penalty
+            T QL[3][5];
+            for (int i = 0; i < 3; ++i)
+              for (int v = 0; v < 5; ++v) QL[i][v] = Gf[(((sL * 6 + f) * Nfp + k) * 3 + i) * 5 + v];
+            T Fv[3][5];
+            const T mut = nut.empty() ? T(0) : UL[0] * (nut[e] + nut[eR]) / 2;
+            viscous_flux<T>(UL, QL, gas, Fv, mut, prandtl_t);
+            for (int v = 0; v < 5; ++v)
+              Fvn[v] = Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2] + ldg_tau * (UR[v] - UL[v]);
+          } else if (viscous) {
             const T JL = Jf[(sL * 6 + f) * Nfp + k], JR = Jf[(sR * 6 + fR) * Nfp + kR];
             T GI[3][5];
             for (int i = 0; i < 3; ++i)
@@ -1178,6 +1257,14 @@ void *ora_create(int prec, int p, int64_t n_elem, const int64_t *elem_vert, int 
 void ora_destroy(void *h) { delete static_cast<Iface *>(h); }
 
 int ora_n_features(void *h) { return static_cast<Iface *>(h)->n_features(); }
+
+// viscous scheme: 0 BR2 (default), 1 LDG with penalty tau
+int ora_set_viscous_scheme(void *h, int scheme, double tau) {
+  Iface *o = static_cast<Iface *>(h);
+  int rc = o->set_viscous_scheme(scheme, tau);
+  if (rc) g_err = o->last_err();
+  return rc;
+}
 
 // body force per unit mass g[3] (the source term of Eq. (3)); zero switches it off
 int ora_set_body_force(void *h, const double *g) {
