@@ -49,7 +49,23 @@ enum fr_flux { FR_RUSANOV = 0, FR_ROE = 1 };     /* interface Riemann solver */
 enum fr_prec { FR_FP64 = 0, FR_FP32 = 1 };       /* FP32: operators and fluxes in FP32 with a
                                                     reference-state split; state, RK registers
                                                     and the mass equation in FP64 */
-enum fr_scheme { FR_RK4 = 0, FR_LSRK45 = 1 };    /* classical RK4; Carpenter-Kennedy 5-stage 2N */
+/* Common viscous flux (section "FR Algorithm"):
+ *   FR_BR2  the second Bassi-Rebay scheme: common gradient = mean of the two broken gradients
+ *           plus the two local liftings of the jump, with factor br2_eta;
+ *   FR_LDG  the local DG scheme the paper uses (after Huynh): the common solution is one-sided,
+ *           U^ = the trace of the face's non-owner (beta = +n_owner/2; the owner is the side with
+ *           the smaller element index, then local face), each side's corrected gradient uses
+ *           U^ - U, and the common viscous normal flux is the owner's F_v(U_L, q_L) . n plus
+ *           ldg_tau (U_R - U_L). */
+enum fr_viscous { FR_BR2 = 0, FR_LDG = 1 };
+
+enum fr_scheme {                                  /* explicit Runge-Kutta schemes: */
+  FR_RK4 = 0,      /* classical four-stage RK4 (three registers) */
+  FR_LSRK45 = 1,   /* Carpenter-Kennedy five-stage fourth-order, 2N storage */
+  FR_SSPRK104 = 2  /* Ketcheson's ten-stage fourth-order strong-stability-preserving method
+                      in its two-register low-storage form (SSP coefficient 6), the class of
+                      scheme the paper advances in time with (section "FR Algorithm") */
+};
 
 /* Mesh and physics description, read by fr_mesh_create (section "FR Algorithm", Eq. (1)).
  *   p          polynomial degree of the solution, 0..7.
@@ -64,6 +80,9 @@ enum fr_scheme { FR_RK4 = 0, FR_LSRK45 = 1 };    /* classical RK4; Carpenter-Ken
  *   gamma, prandtl   ratio of specific heats and Prandtl number.
  *   mu         dynamic viscosity (constant); mu == 0 gives the Euler equations.
  *   br2_eta    BR2 penalty factor (the number of faces, 6, is the usual choice).
+ *   viscous    enum fr_viscous: the common viscous flux (0 = BR2; zero-initialised descriptors
+ *              keep it). FR_LDG needs prec = FR_FP64 (FR_ERR_UNSUPPORTED otherwise).
+ *   ldg_tau    LDG penalty (>= 0) on the jump of every conserved variable.
  *   flux       enum fr_flux.   prec: enum fr_prec.
  *   check_finite  non-zero: fr_residual scans its result and reports FR_ERR_NONFINITE.
  *   ref_rho, ref_p  reference state at rest used by FR_FP32 (ignored by FR_FP64): the FP32
@@ -84,9 +103,10 @@ typedef struct {
   int32_t flux;
   int32_t prec;
   int32_t check_finite;
-  int32_t reserved; /* must be 0 */
+  int32_t viscous;
   double ref_rho;
   double ref_p;
+  double ldg_tau;
 } fr_mesh_desc;
 
 /* Build a mesh on the current HIP device: pair faces (sort-and-match on corner ids, as the
@@ -110,7 +130,12 @@ int fr_sol_coords(fr_mesh_t m, double *xyz);
 int fr_set_state(fr_mesh_t m, const double *U, int on_device);
 int fr_get_state(fr_mesh_t m, double *U, int on_device);
 
-/* R = dQ/dt of Eq. (3) (source term 0) for the handle's current state, always in double
+/* Source term S of Eq. (3) as a constant body force per unit mass g[3] ("body forcing" is
+ * among the solver's physical models, section "ZFR Framework"): S = (0, rho g, m . g), added
+ * to every later residual and RK stage. g = NULL or all zeros switches it off. */
+int fr_set_body_force(fr_mesh_t m, const double *g);
+
+/* R = dQ/dt of Eq. (3) (with the source term, if set) for the handle's current state, always in double
  * precision, layout [n_elem][5][N_s]. Errors: FR_ERR_ARG, FR_ERR_HIP, FR_ERR_NONFINITE. */
 int fr_residual(fr_mesh_t m, double *R, int on_device);
 

@@ -135,6 +135,70 @@ __device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], c
 }
 
 // ------------------------------------------------------------------------------------------
+// Fused epilogue of the volume kernels: the source term and the RK register update of one
+// point, in double precision.
+// ------------------------------------------------------------------------------------------
+
+// Body force g per unit mass (the source term S of Eq. (3)): rho g in the momentum, m . g in
+// the energy, from the point's state X.
+__device__ __forceinline__ void add_body_force(const StageArgs &st, const double X[5], double R[5]) {
+  if (st.force) {
+    R[1] += X[0] * st.g[0];
+    R[2] += X[0] * st.g[1];
+    R[3] += X[0] * st.g[2];
+    R[4] += X[1] * st.g[0] + X[2] * st.g[1] + X[3] * st.g[2];
+  }
+}
+
+// Whether a stage reads the first register (LSRK dU, RK4 accumulator, SSP q2) and the second
+// (RK4 Q).
+__device__ __forceinline__ bool rk_reads_r1(const StageArgs &st) {
+  if (st.mode == kModeLSRK || st.mode == kModeRK4) return !st.first;
+  return st.mode == kModeSSP && (st.stage == 4 || st.stage == 9);
+}
+__device__ __forceinline__ bool rk_reads_r2(const StageArgs &st) { return st.mode == kModeRK4; }
+
+// x: the state the stage was evaluated on; R: its residual; r1, r2: the registers' old values.
+//   LSRK45:   dU <- a dU + dt R; U <- x + b dU                       (out0 = U, reg1 = dU)
+//   RK4:      acc <- acc + w R; S <- Q + c dt R, or at the last stage Q <- Q + dt acc
+//                                                (out0 = Q, reg1 = acc, reg2 = S)
+//   SSP(10,4) (out0 = q1 = U, reg1 = q2): stages 0-3 and 5-8 take a forward-Euler step
+//             q1 <- q1 + dt/6 R (stage 0 also sets q2 <- q1); stage 4 then combines
+//             q2 <- q2/25 + 9/25 q1, q1 <- 15 q2 - 5 q1; stage 9 sets q1 <- q2 + 3/5 q1 + dt/10 R.
+__device__ __forceinline__ void rk_store(const StageArgs &st, int64_t o, double x, double R, double r1, double r2,
+                                         double *out0, double *reg1, double *reg2) {
+  if (st.mode == kModeResidual) {
+    out0[o] = R;
+  } else if (st.mode == kModeLSRK) {
+    const double du = st.a * r1 + st.dt * R;
+    reg1[o] = du;
+    out0[o] = x + st.b * du;
+  } else if (st.mode == kModeRK4) {
+    const double acc = r1 + st.w * R;
+    if (!st.last) {
+      reg1[o] = acc;
+      reg2[o] = r2 + st.cdt * R;
+    } else {
+      out0[o] = r2 + st.dt * acc;
+    }
+  } else {
+    if (st.stage == 9) {
+      out0[o] = r1 + 0.6 * x + st.dt / 10 * R;
+    } else {
+      const double q1 = x + st.dt / 6 * R;
+      if (st.stage == 4) {
+        const double q2 = r1 / 25 + 9.0 / 25 * q1;
+        reg1[o] = q2;
+        out0[o] = 15 * q2 - 5 * q1;
+      } else {
+        if (st.stage == 0) reg1[o] = x;
+        out0[o] = q1;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Kernel configuration
 // ------------------------------------------------------------------------------------------
 template <int P>

@@ -78,16 +78,20 @@ struct FaceRec {
 enum StageMode : int32_t {
   kModeResidual = 0,  // write R
   kModeLSRK = 1,      // dU <- a dU + dt R; U <- U + b dU   (a == 0: dU is not read)
-  kModeRK4 = 2        // acc <- (first ? 0 : acc) + w R; S <- Q + cdt R, or Q <- Q + dt acc
+  kModeRK4 = 2,       // acc <- (first ? 0 : acc) + w R; S <- Q + cdt R, or Q <- Q + dt acc
+  kModeSSP = 3        // ten-stage SSP method, two registers q1 = U and q2 (see rk_store)
 };
 
 struct StageArgs {
   int32_t mode;
   int32_t first;  // RK4: first stage (acc not read); LSRK: a == 0
   int32_t last;   // RK4: last stage (Q updated instead of S)
-  int32_t pad;
+  int32_t stage;  // SSP: stage index 0..9
   double a, b, dt;  // LSRK coefficients and step
   double w, cdt;    // RK4 weight and next-stage offset c_{i+1} * dt
+  double g[3];      // body force per unit mass (source term), applied when force != 0
+  int32_t force;
+  int32_t pad;
 };
 
 // Device buffers of one mesh (FP64 or FP32 operator path; the state is always FP64).
@@ -121,6 +125,10 @@ struct DeviceMesh {
   void *fout32 = nullptr;   // [F][9][Nfp] float: J (5), owner's momentum flux (3), reduced energy flux
   void *foutm = nullptr;    // [F][Nfp] double: owner's mass flux
   double ref_rho = 1.0, ref_p = 0.0;
+  bool ldg = false;             // LDG common viscous flux (else BR2)
+  double ldg_tau = 0.0;
+  double force[3] = {0, 0, 0};  // body force per unit mass (source term S)
+  bool has_force = false;
   // learned eddy-viscosity closure (FP64 path only)
   int sgs = 0;                 // 0 off, 1 fixed per-element nu_t, 2 nu_t from the model per stage
   double *nut = nullptr;       // [E] eddy kinematic viscosity

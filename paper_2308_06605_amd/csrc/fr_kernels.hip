@@ -111,11 +111,11 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void 
 // Writes J = (U_R - U_L)/2 = U^C - U_L and the owner's transformed common normal flux
 // F^{I,perp}_L = |N| (F*_inv - F_v(U^C, G^I) . n) to a face-major buffer [F][10][Nfp].
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC, bool SGS>
+template <int P, typename real, bool VISC, bool SGS, bool LDG>
 __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
                                               const FaceRec *__restrict__ ftab, int64_t F, Phys<real> ph,
                                               int flux, real *__restrict__ fout, const double *__restrict__ nut,
-                                              real kt) {
+                                              real kt, real tau) {
   constexpr int N = P + 1, NFP = N * N;
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t fc = gid / NFP;
@@ -143,7 +143,26 @@ __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 #pragma unroll
   for (int v = 0; v < 5; ++v) UC[v] = real(0.5) * (UL[v] + UR[v]);
   real Fvn[5] = {0, 0, 0, 0, 0};
-  if (VISC) {
+  if (VISC && LDG) {
+    // LDG: the owner's viscous flux with its corrected gradient (the gradient slots of the face
+    // buffer hold it), plus the penalty on the jump
+    real QL[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) QL[i][v] = srcL[(5 + i * 5 + v) * NFP];
+    real Fv[3][5];
+    real mu = ph.mu, kap = ph.kappa;
+    if (SGS) {
+      const real mut = UL[0] * real(0.5 * (nut[r.eL] + nut[r.eR]));
+      mu += mut;
+      kap += mut * kt;
+    }
+    visc_flux_mk(UL, QL, ph.gm1, mu, kap, Fv);
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      Fvn[v] = Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2] + tau * (UR[v] - UL[v]);
+  } else if (VISC) {
     // BR2: mean of the broken gradients plus the two face liftings, which combine to
     // sigma N (U_R - U_L) with N the owner's normal
     const real sig = fg[3 * NFP];
@@ -172,7 +191,8 @@ __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
   real *dst = fout + (fc * 10) * NFP + kk;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    dst[v * NFP] = real(0.5) * (UR[v] - UL[v]);
+    // U^ - U_L: the mean (BR2) or the non-owner's trace (LDG)
+    dst[v * NFP] = LDG ? UR[v] - UL[v] : real(0.5) * (UR[v] - UL[v]);
     dst[(5 + v) * NFP] = nm * (Fi[v] - Fvn[v]);
   }
 }
@@ -183,7 +203,7 @@ __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 // transformed divergence sum_n D_n F^n plus the flux correction
 // (s F^{I,perp} - F^d_f) g'(xi_d), R = -div/|J|, and the RK register update.
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC, bool SGS>
+template <int P, typename real, bool VISC, bool SGS, bool LDG>
 __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k_volume(
     const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
@@ -226,12 +246,15 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k
         const int uu = swp ? b : a, vv = swp ? a : b;
         const int kc = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
         const real *src = fout + ((int64_t)fr.fid * 10) * NFP + kc;
-        const real sgn = ((fr.code >> 6) & 1) ? real(1) : real(-1);
+        const bool own = (fr.code >> 6) & 1;
+        const real sgn = own ? real(1) : real(-1);
         const real sfl = (f & 1) ? sgn : -sgn;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          // c < 5: owner's flux -> s F^{I,perp}_own; c >= 5: jump -> U^C - U_own
-          gv[r][c] = c < 5 ? sfl * src[(5 + c) * NFP] : sgn * src[(c - 5) * NFP];
+          // c < 5: owner's flux -> s F^{I,perp}_own; c >= 5: jump -> U^ - U_own (LDG: U_R - U_L
+          // on the owner's side, 0 on the other)
+          gv[r][c] = c < 5 ? sfl * src[(5 + c) * NFP]
+                           : (LDG ? (own ? src[(c - 5) * NFP] : real(0)) : sgn * src[(c - 5) * NFP]);
         }
       }
     }
@@ -318,15 +341,11 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k
   }
   // the RK registers are loaded here so that their latency overlaps the divergence phase
   if (act) {
-    if (st.mode == kModeLSRK) {
+    const bool l1 = rk_reads_r1(st), l2 = rk_reads_r2(st);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) r1[v] = st.first ? 0.0 : reg1[base + v * NS];
-    } else if (st.mode == kModeRK4) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        r1[v] = st.first ? 0.0 : reg1[base + v * NS];
-        r2[v] = out0[base + v * NS];
-      }
+    for (int v = 0; v < 5; ++v) {
+      r1[v] = l1 ? reg1[base + v * NS] : 0.0;
+      r2[v] = l2 ? out0[base + v * NS] : 0.0;
     }
   }
   // divergence of the transformed flux and the flux correction, one direction at a time
@@ -375,27 +394,111 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k
     }
   }
   if (!act) return;
-  // R = -div / |J| and the RK register update
+  // R = -div / |J| plus the source, and the RK register update
+  double Rv[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const double R = -double(div[v]) * double(iJ);
-    const int64_t o = base + v * NS;
-    if (st.mode == kModeResidual) {
-      out0[o] = R;
-    } else if (st.mode == kModeLSRK) {
-      // out0 = U (the state this stage was evaluated on, Xd), reg1 = dU
-      const double du = st.a * r1[v] + st.dt * R;
-      reg1[o] = du;
-      out0[o] = Xd[v] + st.b * du;
-    } else {
-      // RK4: out0 = Q (r2), reg1 = accumulator (r1), reg2 = stage state S
-      const double acc = r1[v] + st.w * R;
-      if (!st.last) {
-        reg1[o] = acc;
-        reg2[o] = r2[v] + st.cdt * R;
+  for (int v = 0; v < 5; ++v) Rv[v] = -double(div[v]) * double(iJ);
+  add_body_force(st, Xd, Rv);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) rk_store(st, base + v * NS, Xd[v], Rv[v], r1[v], r2[v], out0, reg1, reg2);
+}
+
+// ------------------------------------------------------------------------------------------
+// LDG: each element's corrected gradient (section "FR Algorithm", the viscous flux by the local
+// DG method). The common solution is the face non-owner's trace, so U^ - U_K = U_R - U_L on
+// the faces the element owns and 0 on the others. The corrected physical gradient is
+// interpolated to the element's face points, into the gradient slots of its own face-buffer
+// entries; the face kernel reads the owner's. Runs after a pre-pass that wrote U_f only.
+// ------------------------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_ldg_grad(const double *__restrict__ X,
+                                                             const double *__restrict__ geo,
+                                                             const FaceRef *__restrict__ fref,
+                                                             const FaceRec *__restrict__ ftab,
+                                                             double *__restrict__ face, int64_t E,
+                                                             OpsT<double> ops) {
+  using C = Cfg<P>;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  __shared__ double sU[EPB][5][NS];
+  __shared__ double sJ[EPB][5][NF];
+  __shared__ double sG[EPB][15][NS];
+  const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const bool act = e < E;
+  const int idx[3] = {t % N, (t / N) % N, t / (N * N)};
+  double ja[9], iJ = 0;
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sU[slot][v][t] = X[(e * 5 + v) * NS + t];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ja[c] = geo[(e * 10 + c) * NS + t];
+    iJ = geo[(e * 10 + 9) * NS + t];
+    for (int fp = t; fp < NF; fp += NS) {
+      const int f = fp / NFP, kk = fp - f * NFP;
+      const FaceRef fr = fref[e * 6 + f];
+      if ((fr.code >> 6) & 1) {
+        const FaceRec r = ftab[fr.fid];
+        const int fR = (r.code >> 3) & 7;
+        const bool swp = (r.code >> 6) & 1, flu = (r.code >> 7) & 1, flv = (r.code >> 8) & 1;
+        const int a = kk % N, b = kk / N;
+        const int uu = swp ? b : a, vv = swp ? a : b;
+        const int kr = (flu ? P - uu : uu) + N * (flv ? P - vv : vv);
+        const double *own = face + ((e * 6 + f) * 20) * NFP + kk;
+        const double *nbr = face + (((int64_t)r.eR * 6 + fR) * 20) * NFP + kr;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sJ[slot][v][fp] = nbr[v * NFP] - own[v * NFP];
       } else {
-        out0[o] = r2[v] + st.dt * acc;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sJ[slot][v][fp] = 0.0;
       }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    double dU[3][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        d0 += ops.D[idx[0] * N + c] * sU[slot][v][c + N * (idx[1] + N * idx[2])];
+        d1 += ops.D[idx[1] * N + c] * sU[slot][v][idx[0] + N * (c + N * idx[2])];
+        d2 += ops.D[idx[2] * N + c] * sU[slot][v][idx[0] + N * (idx[1] + N * c)];
+      }
+      dU[0][v] = d0;
+      dU[1][v] = d1;
+      dU[2][v] = d2;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
+      const int kk = idx[u] + N * idx[w];
+      const double cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        dU[d][v] += sJ[slot][v][(2 * d) * NFP + kk] * cL + sJ[slot][v][(2 * d + 1) * NFP + kk] * cR;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        sG[slot][i * 5 + v][t] = iJ * (ja[i] * dU[0][v] + ja[3 + i] * dU[1][v] + ja[6 + i] * dU[2][v]);
+  }
+  __syncthreads();
+  if (!act) return;
+  // items (gradient component i, face point): 5 values each
+  for (int q = t; q < 3 * NF; q += NS) {
+    const int i = q / NF, fp = q - i * NF;
+    const int f = fp / NFP, kk = fp - f * NFP;
+    const int a = kk % N, b = kk / N, d = f >> 1;
+    const double *ell = (f & 1) ? ops.lp : ops.lm;
+    double *dst = face + ((e * 6 + f) * 20 + 5 + 5 * i) * NFP + kk;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][i * 5 + v][line_pt<N>(d, c, a, b)];
+      dst[v * NFP] = acc;
     }
   }
 }
@@ -622,7 +725,7 @@ static int features(DeviceMesh &dm, const double *X, float *feat) {
   }
 }
 
-template <int P, typename real, bool VISC, bool SGS>
+template <int P, typename real, bool VISC, bool SGS, bool LDG>
 static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
                           double *ms) {
   using C = Cfg<P>;
@@ -645,15 +748,24 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], s));
   }
-  hipLaunchKernelGGL((k_prepass<P, real, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+  hipLaunchKernelGGL((k_prepass<P, real, VISC && !LDG>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
                      (const real *)dm.geo, (real *)dm.face, dm.E, ops);
   HIPCHK(hipGetLastError());
+  if (LDG) {
+    static_assert(sizeof(OpsT<double>) == sizeof(Ops1D), "operator tables share one layout");
+    OpsT<double> od;
+    std::memcpy(&od, &dm.ops, sizeof od);
+    hipLaunchKernelGGL((k_ldg_grad<P>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X, (const double *)dm.geo,
+                       dm.fref, dm.ftab, (double *)dm.face, dm.E, od);
+    HIPCHK(hipGetLastError());
+  }
   if (ms) HIPCHK(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL((k_face<P, real, VISC, SGS>), dim3((unsigned)fblocks), dim3(256), 0, s, (const real *)dm.face,
-                     (const real *)dm.fgeo, dm.ftab, dm.F, ph, dm.flux, (real *)dm.fout, dm.nut, kt);
+  hipLaunchKernelGGL((k_face<P, real, VISC, SGS, LDG>), dim3((unsigned)fblocks), dim3(256), 0, s,
+                     (const real *)dm.face, (const real *)dm.fgeo, dm.ftab, dm.F, ph, dm.flux, (real *)dm.fout,
+                     dm.nut, kt, real(dm.ldg_tau));
   HIPCHK(hipGetLastError());
   if (ms) HIPCHK(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL((k_volume<P, real, VISC, SGS>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+  hipLaunchKernelGGL((k_volume<P, real, VISC, SGS, LDG>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
                      (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1, reg2,
                      dm.nut, kt);
   HIPCHK(hipGetLastError());
@@ -670,24 +782,26 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
   return FR_OK;
 }
 
-template <typename real, bool VISC, bool SGS>
+template <typename real, bool VISC, bool SGS, bool LDG>
 static int launch_stage_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
                           double *ms) {
   switch (dm.p) {
-    case 0: return launch_stage_t<0, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
-    case 1: return launch_stage_t<1, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
-    case 2: return launch_stage_t<2, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
-    case 3: return launch_stage_t<3, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
-    case 4: return launch_stage_t<4, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
-    case 5: return launch_stage_t<5, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
-    case 6: return launch_stage_t<6, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
-    case 7: return launch_stage_t<7, real, VISC, SGS>(dm, X, st, o, r1, r2, ms);
+    case 0: return launch_stage_t<0, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 1: return launch_stage_t<1, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 2: return launch_stage_t<2, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 3: return launch_stage_t<3, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 4: return launch_stage_t<4, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 5: return launch_stage_t<5, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 6: return launch_stage_t<6, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 7: return launch_stage_t<7, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
     default: return fail(FR_ERR_UNSUPPORTED, "p out of range");
   }
 }
 
 static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
                         double *ms = nullptr) {
+  st.force = dm.has_force ? 1 : 0;
+  for (int i = 0; i < 3; ++i) st.g[i] = dm.force[i];
   if (dm.prec == FR_FP32) {
     std::string err;
     int rc = launch_stage32(dm, X, st, o, r1, r2, ms, err);
@@ -701,10 +815,12 @@ static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o
       rc = mlp_forward_nu(dm.model, dm.feat, dm.E, dm.Ns + 4, dm.nut, dm.nu_scale, dm.stream);
       if (rc) return rc;
     }
-    return launch_stage_p<double, true, true>(dm, X, st, o, r1, r2, ms);
+    return dm.ldg ? launch_stage_p<double, true, true, true>(dm, X, st, o, r1, r2, ms)
+                  : launch_stage_p<double, true, true, false>(dm, X, st, o, r1, r2, ms);
   }
-  return dm.viscous ? launch_stage_p<double, true, false>(dm, X, st, o, r1, r2, ms)
-                    : launch_stage_p<double, false, false>(dm, X, st, o, r1, r2, ms);
+  if (!dm.viscous) return launch_stage_p<double, false, false, false>(dm, X, st, o, r1, r2, ms);
+  return dm.ldg ? launch_stage_p<double, true, false, true>(dm, X, st, o, r1, r2, ms)
+                : launch_stage_p<double, true, false, false>(dm, X, st, o, r1, r2, ms);
 }
 
 // Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients.
@@ -758,6 +874,20 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
         if (rc) return rc;
         if (ms_acc) ms_acc[3] += 1;
       }
+    } else if (scheme == FR_SSPRK104) {
+      if (!dm.R1) {
+        HIPCHK(hipMalloc(&dm.R1, M * sizeof(double)));
+        dm.bytes += M * sizeof(double);
+      }
+      for (int s = 0; s < 10; ++s) {
+        StageArgs st{};
+        st.mode = kModeSSP;
+        st.stage = s;
+        st.dt = dt;
+        int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, ms_acc);
+        if (rc) return rc;
+        if (ms_acc) ms_acc[3] += 1;
+      }
     } else {
       return fail(FR_ERR_ARG, "unknown scheme");
     }
@@ -783,7 +913,10 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
     return fail(FR_ERR_ARG, "FR_FP32 needs ref_rho > 0 and ref_p >= 0");
   if (!(d->gamma > 1.0) || !(d->prandtl > 0.0) || !(d->mu >= 0.0) || !(d->br2_eta >= 0.0))
     return fail(FR_ERR_ARG, "gamma > 1, prandtl > 0, mu >= 0 and br2_eta >= 0 are required");
-  if (d->reserved != 0) return fail(FR_ERR_ARG, "reserved must be 0");
+  if (d->viscous != FR_BR2 && d->viscous != FR_LDG) return fail(FR_ERR_ARG, "unknown viscous scheme");
+  if (d->viscous == FR_LDG && d->prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "FR_LDG needs prec = FR_FP64");
+  if (d->viscous == FR_LDG && !(d->ldg_tau >= 0.0 && std::isfinite(d->ldg_tau)))
+    return fail(FR_ERR_ARG, "ldg_tau must be finite and >= 0");
 
   HostMesh H;
   std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->br2_eta, H);
@@ -801,6 +934,8 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   dm.flux = d->flux;
   dm.viscous = d->mu > 0.0;
   dm.eta = d->br2_eta;
+  dm.ldg = d->viscous == FR_LDG;
+  dm.ldg_tau = dm.ldg ? d->ldg_tau : 0.0;
   dm.phys = Physics{d->gamma, d->prandtl, d->mu, d->mu * d->gamma / (d->prandtl * (d->gamma - 1.0))};
   dm.ops = H.ops;
   dm.sgs_ops = sgs_ops(d->p);
@@ -1034,6 +1169,21 @@ int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_b
   if (n_elem) *n_elem = m->dm.E;
   if (n_sol) *n_sol = m->dm.Ns;
   if (device_bytes) *device_bytes = m->dm.bytes;
+  return FR_OK;
+}
+
+int fr_set_body_force(fr_mesh_t m, const double *g) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  DeviceMesh &dm = m->dm;
+  if (!g) {
+    dm.has_force = false;
+    for (int i = 0; i < 3; ++i) dm.force[i] = 0.0;
+    return FR_OK;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(g[i])) return fail(FR_ERR_ARG, "body force must be finite");
+  for (int i = 0; i < 3; ++i) dm.force[i] = g[i];
+  dm.has_force = g[0] != 0.0 || g[1] != 0.0 || g[2] != 0.0;
   return FR_OK;
 }
 

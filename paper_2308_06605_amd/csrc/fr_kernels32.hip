@@ -399,15 +399,11 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) Fm[d] = jad[d * 3 + 0] * Xd[1] + jad[d * 3 + 1] * Xd[2] + jad[d * 3 + 2] * Xd[3];
-    if (st.mode == kModeLSRK) {
+    const bool l1 = rk_reads_r1(st), l2 = rk_reads_r2(st);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) r1[v] = st.first ? 0.0 : reg1[base + v * NS];
-    } else if (st.mode == kModeRK4) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        r1[v] = st.first ? 0.0 : reg1[base + v * NS];
-        r2[v] = out0[base + v * NS];
-      }
+    for (int v = 0; v < 5; ++v) {
+      r1[v] = l1 ? reg1[base + v * NS] : 0.0;
+      r2[v] = l2 ? out0[base + v * NS] : 0.0;
     }
   }
   float div[5] = {0, 0, 0, 0, 0};
@@ -479,26 +475,9 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
   Rv[2] = -double(div[2]) * iJd;
   Rv[3] = -double(div[3]) * iJd;
   Rv[4] = -double(div[4]) * iJd + ref.H_d * Rv[0];
+  add_body_force(st, Xd, Rv);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const double Rr = Rv[v];
-    const int64_t o = base + v * NS;
-    if (st.mode == kModeResidual) {
-      out0[o] = Rr;
-    } else if (st.mode == kModeLSRK) {
-      const double du = st.a * r1[v] + st.dt * Rr;
-      reg1[o] = du;
-      out0[o] = Xd[v] + st.b * du;
-    } else {
-      const double acc = r1[v] + st.w * Rr;
-      if (!st.last) {
-        reg1[o] = acc;
-        reg2[o] = r2[v] + st.cdt * Rr;
-      } else {
-        out0[o] = r2[v] + st.dt * acc;
-      }
-    }
-  }
+  for (int v = 0; v < 5; ++v) rk_store(st, base + v * NS, Xd[v], Rv[v], r1[v], r2[v], out0, reg1, reg2);
 }
 
 #define HIPCHK32(call)                                           \

@@ -19,7 +19,7 @@ ERRORS = {-1: "FR_ERR_ARG", -2: "FR_ERR_MESH", -3: "FR_ERR_HIP", -4: "FR_ERR_OOM
           -5: "FR_ERR_UNSUPPORTED", -6: "FR_ERR_NONFINITE"}
 FLUX = {"rusanov": 0, "roe": 1}
 PREC = {"fp64": 0, "fp32": 1}
-SCHEME = {"rk4": 0, "lsrk45": 1}
+SCHEME = {"rk4": 0, "lsrk45": 1, "ssprk104": 2}
 
 
 class FRError(RuntimeError):
@@ -35,8 +35,8 @@ class fr_mesh_desc(ctypes.Structure):
         ("elem_vert", ctypes.c_void_p), ("elem_nodes", ctypes.c_void_p),
         ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double), ("mu", ctypes.c_double),
         ("br2_eta", ctypes.c_double), ("flux", ctypes.c_int32), ("prec", ctypes.c_int32),
-        ("check_finite", ctypes.c_int32), ("reserved", ctypes.c_int32),
-        ("ref_rho", ctypes.c_double), ("ref_p", ctypes.c_double),
+        ("check_finite", ctypes.c_int32), ("viscous", ctypes.c_int32),
+        ("ref_rho", ctypes.c_double), ("ref_p", ctypes.c_double), ("ldg_tau", ctypes.c_double),
     ]
 
 
@@ -51,6 +51,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2308_06605_amd.build`"
                            " (or __graft_entry__.build()); there is no fallback path")
+    # torch ships a HIP runtime with the same soname as the system one libfr links against; the
+    # first one loaded serves the whole process, so let torch load and initialise its runtime
+    # before libfr, as torch's own GPU calls (streams, allocations) need it
+    import torch
+
+    torch.cuda.is_available()
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     L.fr_last_error.restype = ctypes.c_char_p
@@ -67,6 +73,7 @@ def load():
     L.fr_mesh_geometry_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, P, P, P, P]
     L.fr_basis_host.argtypes = [i32, P, P, P, P, P]
     L.fr_kinetic_energy.argtypes = [P, P]
+    L.fr_set_body_force.argtypes = [P, P]
     # learned eddy-viscosity closure
     L.fr_sgs_n_features.argtypes = [i32]
     L.fr_sgs_features.argtypes = [P, P]
@@ -86,7 +93,7 @@ def load():
     L.fr_mlp_train_step.argtypes = [P, P, i64, i64, P, ctypes.c_float, P]
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
-                 "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy", "fr_sgs_n_features",
+                 "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
                  "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
                  "fr_mlp_get_params", "fr_mlp_get_bf16", "fr_mlp_forward", "fr_mlp_loss_grad",
@@ -107,15 +114,19 @@ def _current_stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, ref=(1.0, 0.0)):
+VISCOUS = {"br2": 0, "ldg": 1}
+
+
+def _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, ref=(1.0, 0.0), viscous="br2",
+          ldg_tau=0.1):
     ev = np.ascontiguousarray(mesh.elem_vert, dtype=np.int64)
     nodes = np.ascontiguousarray(mesh.elem_nodes, dtype=np.float64)
     keep.extend([ev, nodes])
     return fr_mesh_desc(p=int(p), q=int(mesh.q), n_elem=int(ev.shape[0]), elem_vert=ev.ctypes.data,
                         elem_nodes=nodes.ctypes.data, gamma=gamma, prandtl=prandtl, mu=mu,
                         br2_eta=eta, flux=FLUX[flux], prec=PREC[prec],
-                        check_finite=int(bool(check_finite)), reserved=0,
-                        ref_rho=float(ref[0]), ref_p=float(ref[1]))
+                        check_finite=int(bool(check_finite)), viscous=VISCOUS[viscous],
+                        ref_rho=float(ref[0]), ref_p=float(ref[1]), ldg_tau=float(ldg_tau))
 
 
 def geometry_host(mesh, p: int, eta: float = 6.0):
@@ -146,13 +157,15 @@ class FRMesh:
 
     def __init__(self, mesh, p: int, *, mu: float = 0.0, gamma: float = 1.4, prandtl: float = 0.72,
                  eta: float = 6.0, flux: str = "rusanov", prec: str = "fp64", check_finite: bool = False,
-                 stream=None, ref_rho: float = 1.0, ref_p: float = 0.0):
+                 stream=None, ref_rho: float = 1.0, ref_p: float = 0.0, viscous: str = "br2",
+                 ldg_tau: float = 0.1):
         L = load()
         self.p = int(p)
         self.Ns = (self.p + 1) ** 3
         self.E = int(mesh.elem_vert.shape[0])
         keep = []
-        d = _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, (ref_rho, ref_p))
+        d = _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, (ref_rho, ref_p), viscous,
+                  ldg_tau)
         self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
         h = ctypes.c_void_p()
         _check(L.fr_mesh_create(ctypes.byref(d), self._stream, ctypes.byref(h)))
@@ -223,6 +236,15 @@ class FRMesh:
         out = np.zeros(2)
         _check(load().fr_kinetic_energy(self.h, out.ctypes.data))
         return float(out[0]), float(out[1])
+
+    def set_body_force(self, g):
+        """Constant body force per unit mass (3 values; None or zeros switch it off)."""
+        if g is None:
+            _check(load().fr_set_body_force(self.h, None))
+            return
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert g.shape == (3,)
+        _check(load().fr_set_body_force(self.h, g.ctypes.data))
 
     # ---- learned eddy-viscosity closure ----
     @property

@@ -228,6 +228,74 @@ def random_smooth_perturbation(xyz_e3s: np.ndarray, seed: int, amp: float = 1e-3
     return points_to_state_layout(amp * out)
 
 
+def box_axis_points(mesh: Mesh, p: int):
+    """The distinct solution-point coordinates along each axis of an uncurved box mesh: for
+    axis d, n_d (p+1) values ordered (element index, point index)."""
+    xs = np.polynomial.legendre.leggauss(p + 1)[0]
+    out = []
+    for d in range(3):
+        h = (mesh.hi[d] - mesh.lo[d]) / mesh.shape[d]
+        ie = np.arange(mesh.shape[d])
+        out.append((mesh.lo[d] + h * (ie[:, None] + (xs[None, :] + 1.0) / 2.0)).ravel())
+    return out
+
+
+def grid_to_state_layout(G: np.ndarray, shape, p: int) -> np.ndarray:
+    """A field on the tensor grid of box_axis_points, G[c][z][y][x], -> [E][c][Ns] with element
+    ie + nx (je + ny ke) and point i + n (j + n k)."""
+    nx, ny, nz = shape
+    n = p + 1
+    C = G.shape[0]
+    T = G.reshape(C, nz, n, ny, n, nx, n)               # c, ke, k, je, j, ie, i
+    T = np.transpose(T, (1, 3, 5, 0, 2, 4, 6))          # ke, je, ie, c, k, j, i
+    return np.ascontiguousarray(T.reshape(nx * ny * nz, C, n ** 3))
+
+
+def random_spectrum_state(mesh: Mesh, p: int, seed: int, k0: float = 3.0, kmax: int = 8,
+                          energy: float = 0.125, mach: float = 0.1, gamma: float = GAMMA) -> np.ndarray:
+    """A seeded divergence-free random-phase velocity field on the periodic box [0, 2 pi)^3 at
+    uniform density 1 and pressure 1/(gamma Ma^2), as a state [E][5][Ns] on an uncurved box
+    mesh at degree p.
+
+    u(x) = sum_k Re(c_k exp(i k.x)) over integer wave vectors 0 < |k| <= kmax, with c_k a
+    Gaussian complex vector projected normal to k (so div u = 0) and scaled so that the shell
+    spectrum follows E(k) ~ k^4 exp(-2 (k/k0)^2); the field is then scaled to the mean kinetic
+    energy `energy` (0.125, that of the Taylor-Green vortex) over the points with Gauss weights.
+    Evaluated on the tensor grid of the solution points, one axis at a time.
+    """
+    rng = np.random.default_rng(seed)
+    r = np.arange(-kmax, kmax + 1)
+    KX, KY, KZ = np.meshgrid(r, r, r, indexing="ij")
+    K = np.stack([KX, KY, KZ], axis=-1).astype(np.float64)
+    kk = np.sqrt((K ** 2).sum(axis=-1))
+    mask = (kk > 0) & (kk <= kmax)
+    c = rng.normal(size=K.shape) + 1j * rng.normal(size=K.shape)
+    kh = np.where(mask[..., None], K / np.where(kk > 0, kk, 1.0)[..., None], 0.0)
+    c = c - kh * (c * kh).sum(axis=-1, keepdims=True)        # normal to k
+    amp = np.where(mask, kk * np.exp(-((kk / k0) ** 2)), 0.0)  # |c|^2 ~ k^2 exp(-2 (k/k0)^2)
+    c = c * amp[..., None]
+    ax = box_axis_points(mesh, p)
+    ex = [np.exp(1j * np.outer(r, a)) for a in ax]            # [2 kmax + 1][points on the axis]
+    vel = []
+    for comp in range(3):
+        A = c[..., comp]                                        # [kx][ky][kz]
+        T = np.einsum("abc,cz->abz", A, ex[2])
+        T = np.einsum("abz,by->azy", T, ex[1])
+        T = np.einsum("azy,ax->zyx", T, ex[0])
+        vel.append(T.real)
+    V = grid_to_state_layout(np.stack(vel), mesh.shape, p)      # [E][3][Ns]
+    w = np.polynomial.legendre.leggauss(p + 1)[1]
+    W = np.einsum("k,j,i->kji", w, w, w).ravel()
+    ek = (0.5 * (V ** 2).sum(axis=1) * W).sum() / (W.sum() * V.shape[0])
+    V *= np.sqrt(energy / ek)
+    p0 = 1.0 / (gamma * mach * mach)
+    U = np.empty((V.shape[0], 5, V.shape[2]))
+    U[:, 0] = 1.0
+    U[:, 1:4] = V
+    U[:, 4] = p0 / (gamma - 1.0) + 0.5 * (V ** 2).sum(axis=1)
+    return U
+
+
 # ---------------------------------------------------------------------------------------------
 # Invariance scrambler: random element relabelling plus a random proper rotation of each
 # element's reference frame. The physical mesh and fields are unchanged; only their

@@ -1,0 +1,91 @@
+"""GPU parity of the LDG viscous flux against the oracle, through the C ABI, with the FP64
+floor rule of the plain residual: per variable e_v = max|X_gpu - X_ld| / max|X_ld| <=
+max(1e-12, 4 f_v), f_v the same measure for the double-precision oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_06605_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MU = 1.0 / 1600.0
+TAU = 0.1
+
+
+def _fr():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_06605_amd import fr
+
+    fr.load()
+    return fr
+
+
+def rel(a, b):
+    return np.abs(a - b).max(axis=(0, 2)) / np.maximum(np.abs(b).max(axis=(0, 2)), 1e-300)
+
+
+def _oracles(m, p, flux, mu=MU, nu=None):
+    out = {}
+    for prec in ("f64", "ld"):
+        o = oracle.Oracle(m, p, mu=mu, flux=flux, precision=prec)
+        o.set_viscous_scheme("ldg", TAU)
+        if nu is not None:
+            o.set_eddy_viscosity(nu, 0.9)
+        out[prec] = o
+    return out
+
+
+@pytest.mark.parametrize("p,n,flux", [(3, 5, "roe"), (2, 4, "rusanov"), (4, 3, "roe"), (7, 3, "rusanov"),
+                                      (1, 4, "roe")])
+def test_ldg_residual(p, n, flux):
+    fr = _fr()
+    m = I.box_mesh(n, q=min(p, 3) if p > 1 else 1, curve_amp=0.05, curve_mode="mixed")
+    g = fr.FRMesh(m, p, mu=MU, flux=flux, viscous="ldg", ldg_tau=TAU)
+    X = g.sol_coords()
+    U = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=p, amp=0.02)
+    g.set_state(U)
+    R = g.residual()
+    g.close()
+    o = _oracles(m, p, flux)
+    Rl, Ro = o["ld"].residual(U), o["f64"].residual(U)
+    e, f = rel(R, Rl), rel(Ro, Rl)
+    print(f"LDG p={p} {flux} err {e} floor {f}", flush=True)
+    assert np.all(e <= np.maximum(1e-12, 4 * f)), (e, f)
+
+
+def test_ldg_rk_steps_and_eddy_viscosity():
+    fr = _fr()
+    p = 3
+    m = I.box_mesh(4, q=2, curve_amp=0.05)
+    nu = np.random.default_rng(3).uniform(0, 0.005, m.n_elem)
+    g = fr.FRMesh(m, p, mu=MU, flux="roe", viscous="ldg", ldg_tau=TAU)
+    X = g.sol_coords()
+    U0 = I.state_from_coords(X, I.tgv_state)
+    g.set_state(U0)
+    g.set_eddy_viscosity(nu)
+    R = g.residual()
+    g.rk_step(1e-3, "lsrk45", 2)
+    U2 = g.get_state()
+    g.close()
+    o = _oracles(m, p, "roe", nu=nu)
+    e, f = rel(R, o["ld"].residual(U0)), rel(o["f64"].residual(U0), o["ld"].residual(U0))
+    assert np.all(e <= np.maximum(1e-12, 4 * f)), (e, f)
+    Ul = o["ld"].rk_step(U0, 1e-3, "lsrk45", 2)
+    Uo = o["f64"].rk_step(U0, 1e-3, "lsrk45", 2)
+    e, f = rel(U2, Ul), rel(Uo, Ul)
+    print(f"LDG rk err {e} floor {f}", flush=True)
+    assert np.all(e <= np.maximum(1e-12, 4 * f)), (e, f)
+
+
+def test_ldg_needs_fp64():
+    fr = _fr()
+    m = I.box_mesh(3, q=1)
+    with pytest.raises(fr.FRError) as ei:
+        fr.FRMesh(m, 3, mu=MU, viscous="ldg", prec="fp32", ref_rho=1.0, ref_p=71.4)
+    assert ei.value.name == "FR_ERR_UNSUPPORTED"
+    with pytest.raises(fr.FRError):
+        fr.FRMesh(m, 3, mu=MU, viscous="ldg", ldg_tau=-1.0)
