@@ -184,6 +184,29 @@ int fr_mesh_geometry_host(const fr_mesh_desc *desc, double *geo, double *fgeo, i
 int fr_basis_host(int p, double *D, double *lm, double *lp, double *gcL, double *gcR);
 
 /* ==========================================================================================
+ * Batches: many meshes (any degrees, precisions, closures) advanced together. One RK step of
+ * every mesh is captured once into a HIP graph, each mesh's stage kernels on a branch of its
+ * own, so independent meshes run concurrently; fr_batch_step replays it. The result of every
+ * mesh is bitwise that of fr_rk_step on it alone (same kernels, same order within the mesh).
+ * ========================================================================================== */
+typedef struct fr_batch_s *fr_batch_t;
+
+/* Capture one step of size dt[i] of the given scheme for meshes[i], i < n (distinct handles on
+ * the current device; their RK registers are allocated here). The meshes must outlive the
+ * batch. What lives in device memory may change between steps and is read by every replay:
+ * the state (fr_set_state), the values of a fixed eddy viscosity, a model's parameters. What
+ * the kernels take as arguments is fixed at this call: the step sizes, the body force, and
+ * whether a closure (fixed or model) is attached; change those by creating a new batch.
+ * hip_stream: where fr_batch_step enqueues. Errors: FR_ERR_ARG, FR_ERR_HIP. */
+int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int scheme, void *hip_stream,
+                    fr_batch_t *out);
+
+/* Enqueue n_steps replays of the captured step on the batch's stream (returns without waiting). */
+int fr_batch_step(fr_batch_t b, int n_steps);
+int fr_batch_set_stream(fr_batch_t b, void *hip_stream);
+int fr_batch_destroy(fr_batch_t b);
+
+/* ==========================================================================================
  * Learned eddy-viscosity closure (an LES sub-grid scale model; section "ZFR Framework" lists
  * such models among the solver's physical models without specifying one).
  *

@@ -830,9 +830,29 @@ static const double kLsB[5] = {1432997174477.0 / 9575080441237.0, 5161836677717.
                                1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                                2277821191437.0 / 14882151754819.0};
 
+// Allocate the RK registers a scheme needs (before any graph capture: capture cannot allocate).
+static int ensure_registers(DeviceMesh &dm, int scheme) {
+  const int64_t M = dm.E * 5 * dm.Ns;
+  if (scheme != FR_RK4 && scheme != FR_LSRK45 && scheme != FR_SSPRK104) return fail(FR_ERR_ARG, "unknown scheme");
+  if (!dm.R1) {
+    HIPCHK(hipMalloc(&dm.R1, M * sizeof(double)));
+    dm.bytes += M * sizeof(double);
+  }
+  if (scheme == FR_RK4 && !dm.R2) {
+    HIPCHK(hipMalloc(&dm.R2, M * sizeof(double)));
+    dm.bytes += M * sizeof(double);
+  }
+  return FR_OK;
+}
+
 static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms_acc) {
   DeviceMesh &dm = m->dm;
   const int64_t M = dm.E * 5 * dm.Ns;
+  if (n_steps > 0) {
+    int rc = ensure_registers(dm, scheme);
+    if (rc) return rc;
+  }
+  (void)M;
   for (int step = 0; step < n_steps; ++step) {
     if (scheme == FR_LSRK45) {
       if (!dm.R1) {
@@ -1263,6 +1283,137 @@ int fr_get_eddy_viscosity(fr_mesh_t m, double *nu) {
   hipStream_t s = (hipStream_t)dm.stream;
   HIPCHK(hipMemcpyAsync(nu, dm.nut, dm.E * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return FR_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Batches: one RK step of many meshes captured once into a HIP graph, each mesh's stage
+// kernels on a branch of its own (the meshes are independent, so the branches run
+// concurrently and small meshes share the chip), replayed per step.
+// ------------------------------------------------------------------------------------------
+}  // extern "C"
+
+struct fr_batch_s {
+  uint64_t magic;
+  std::vector<fr_mesh_t> meshes;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+static constexpr uint64_t kBatchMagic = 0x46524241544348ull;  // "FRBATCH"
+
+static bool valid_batch(fr_batch_t b) { return b != nullptr && b->magic == kBatchMagic; }
+
+extern "C" {
+
+int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int scheme, void *hip_stream,
+                    fr_batch_t *out) {
+  if (!out) return fail(FR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!meshes || !dt || n < 1) return fail(FR_ERR_ARG, "need n >= 1 meshes and their dt");
+  if (scheme != FR_RK4 && scheme != FR_LSRK45 && scheme != FR_SSPRK104) return fail(FR_ERR_ARG, "unknown scheme");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  for (int i = 0; i < n; ++i) {
+    if (!valid(meshes[i])) return fail(FR_ERR_ARG, "mesh " + std::to_string(i) + " is not a mesh handle");
+    if (meshes[i]->device != dev) return fail(FR_ERR_ARG, "mesh " + std::to_string(i) + " lives on another device");
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(FR_ERR_ARG, "dt must be finite and > 0");
+    for (int j = 0; j < i; ++j)
+      if (meshes[j] == meshes[i]) return fail(FR_ERR_ARG, "a mesh appears twice in the batch");
+    int rc = ensure_registers(meshes[i]->dm, scheme);
+    if (rc) return rc;
+  }
+  hipStream_t cs = nullptr;
+  std::vector<hipStream_t> br(n, nullptr);
+  std::vector<hipEvent_t> join(n, nullptr);
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int rc = FR_OK;
+  std::string msg;
+  auto chk = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess && rc == FR_OK) {
+      rc = FR_ERR_HIP;
+      msg = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return e == hipSuccess;
+  };
+  bool capturing = false;
+  if (chk(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate") &&
+      chk(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate")) {
+    for (int i = 0; i < n && rc == FR_OK; ++i)
+      if (chk(hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking), "hipStreamCreate"))
+        chk(hipEventCreateWithFlags(&join[i], hipEventDisableTiming), "hipEventCreate");
+  }
+  if (rc == FR_OK && chk(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) {
+    capturing = true;
+    chk(hipEventRecord(fork, cs), "hipEventRecord");
+    for (int i = 0; i < n && rc == FR_OK; ++i) {
+      if (!chk(hipStreamWaitEvent(br[i], fork, 0), "hipStreamWaitEvent")) break;
+      DeviceMesh &dm = meshes[i]->dm;
+      void *saved = dm.stream;
+      dm.stream = br[i];
+      int r = run_steps(meshes[i], dt[i], scheme, 1, nullptr);
+      dm.stream = saved;
+      if (r) {
+        rc = r;
+        msg = g_err;
+        break;
+      }
+      if (!chk(hipEventRecord(join[i], br[i]), "hipEventRecord")) break;
+      chk(hipStreamWaitEvent(cs, join[i], 0), "hipStreamWaitEvent");
+    }
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    capturing = false;
+    chk(e, "hipStreamEndCapture");
+  }
+  (void)capturing;
+  if (rc == FR_OK) chk(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  for (int i = 0; i < n; ++i) {
+    if (join[i]) (void)hipEventDestroy(join[i]);
+    if (br[i]) (void)hipStreamDestroy(br[i]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (rc != FR_OK) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(rc, "batch capture failed: " + msg);
+  }
+  fr_batch_s *b = new fr_batch_s();
+  b->magic = kBatchMagic;
+  b->meshes.assign(meshes, meshes + n);
+  b->stream = (hipStream_t)hip_stream;
+  b->graph = graph;
+  b->exec = exec;
+  b->device = dev;
+  *out = b;
+  return FR_OK;
+}
+
+int fr_batch_step(fr_batch_t b, int n_steps) {
+  if (!valid_batch(b)) return fail(FR_ERR_ARG, "not a batch handle");
+  if (n_steps < 0) return fail(FR_ERR_ARG, "n_steps must be >= 0");
+  for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->exec, b->stream));
+  return FR_OK;
+}
+
+int fr_batch_set_stream(fr_batch_t b, void *hip_stream) {
+  if (!valid_batch(b)) return fail(FR_ERR_ARG, "not a batch handle");
+  b->stream = (hipStream_t)hip_stream;
+  return FR_OK;
+}
+
+int fr_batch_destroy(fr_batch_t b) {
+  if (!b) return FR_OK;
+  if (!valid_batch(b)) return fail(FR_ERR_ARG, "not a batch handle");
+  (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->magic = 0;
+  delete b;
   return FR_OK;
 }
 

@@ -74,6 +74,10 @@ def load():
     L.fr_basis_host.argtypes = [i32, P, P, P, P, P]
     L.fr_kinetic_energy.argtypes = [P, P]
     L.fr_set_body_force.argtypes = [P, P]
+    L.fr_batch_create.argtypes = [P, ctypes.c_int32, P, i32, P, ctypes.POINTER(P)]
+    L.fr_batch_step.argtypes = [P, i32]
+    L.fr_batch_set_stream.argtypes = [P, P]
+    L.fr_batch_destroy.argtypes = [P]
     # learned eddy-viscosity closure
     L.fr_sgs_n_features.argtypes = [i32]
     L.fr_sgs_features.argtypes = [P, P]
@@ -94,6 +98,7 @@ def load():
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
                  "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
+                 "fr_batch_create", "fr_batch_step", "fr_batch_set_stream", "fr_batch_destroy",
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
                  "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
                  "fr_mlp_get_params", "fr_mlp_get_bf16", "fr_mlp_forward", "fr_mlp_loss_grad",
@@ -377,3 +382,33 @@ class MLP:
         assert t.is_cuda and t.is_contiguous() and t.numel() == n and t.element_size() == 4
         lp = ctypes.c_void_p(loss_out.data_ptr()) if loss_out is not None else None
         _check(load().fr_mlp_train_step(self.h, xp, n, ld, ctypes.c_void_p(t.data_ptr()), float(lr), lp))
+
+
+class Batch:
+    """Meshes advanced together by one captured HIP graph per RK step (fr_batch_*)."""
+
+    def __init__(self, meshes, dts, scheme: str = "lsrk45", stream=None):
+        L = load()
+        self.meshes = list(meshes)  # kept alive with the batch
+        n = len(self.meshes)
+        handles = (ctypes.c_void_p * n)(*[m.h.value for m in self.meshes])
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dts, dtype=np.float64), (n,)))
+        self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        h = ctypes.c_void_p()
+        _check(L.fr_batch_create(ctypes.cast(handles, ctypes.c_void_p), n, dt.ctypes.data, SCHEME[scheme],
+                                 self._stream, ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n_steps: int = 1):
+        _check(load().fr_batch_step(self.h, int(n_steps)))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().fr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
