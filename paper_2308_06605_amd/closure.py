@@ -254,17 +254,21 @@ def gen(ic: str, t_end: float, every: float, out: str, keep_state_at=None, refer
         if not reference:
             nuc = rec["nu_closure"][-1]
             extra = (f" | closure-term fit mean {nuc.mean() / NU_SCALE:.3f} zero frac {(nuc == 0).mean():.2f}")
+        _save_gen(out, ic, rec, states)  # after every snapshot, so a cut-off run keeps its data
         log(f"[gen {ic}] t={t:.3f} Ek fine {ek_f:.6f} filtered {rec['ek_filtered'][-1]:.6f} "
             f"eps fine {-dek_f:.5f} nu_t/mu mean {nut.mean() / NU_SCALE:.3f} max {nut.max() / NU_SCALE:.2f} "
             f"zero frac {(nut == 0).mean():.2f}{extra} ({time.time() - t0:.0f} s)")
     gf.close()
     gc.close()
-    np.savez_compressed(out, ic=ic, fine=np.array(FINE), coarse=np.array(COARSE), t=np.array(rec["t"]), nut=np.array(rec["nut"]),
-                        feats=np.array(rec["feats"], dtype=np.float32), ek_filtered=np.array(rec["ek_filtered"]),
-                        ek_fine=np.array(rec["ek_fine"]), dek_fine=np.array(rec["dek_fine"]),
-                        dek_coarse_filtered=np.array(rec["dek_coarse_filtered"]),
-                        nu_closure=np.array(rec.get("nu_closure", [])), **states)
     log(f"[gen {ic}] wrote {out}")
+
+
+def _save_gen(out, ic, rec, states):
+    np.savez_compressed(out, ic=ic, fine=np.array(FINE), coarse=np.array(COARSE), t=np.array(rec["t"]),
+                        nut=np.array(rec["nut"]), feats=np.array(rec["feats"], dtype=np.float32),
+                        ek_filtered=np.array(rec["ek_filtered"]), ek_fine=np.array(rec["ek_fine"]),
+                        dek_fine=np.array(rec["dek_fine"]), dek_coarse_filtered=np.array(rec["dek_coarse_filtered"]),
+                        nu_closure=np.array(rec.get("nu_closure", [])), **states)
 
 
 # ------------------------------------------------------------------------------------------

@@ -139,24 +139,13 @@ __device__ __forceinline__ void visc_flux(const real U[5], const real G[3][5], c
 // point, in double precision.
 // ------------------------------------------------------------------------------------------
 
-// Body force g per unit mass (the source term S of Eq. (3)): rho g in the momentum, m . g in
-// the energy, from the point's state X.
-__device__ __forceinline__ void add_body_force(const StageArgs &st, const double X[5], double R[5]) {
-  if (st.force) {
-    R[1] += X[0] * st.g[0];
-    R[2] += X[0] * st.g[1];
-    R[3] += X[0] * st.g[2];
-    R[4] += X[1] * st.g[0] + X[2] * st.g[1] + X[3] * st.g[2];
-  }
+// Body force g per unit mass (the source term S of Eq. (3)): component v of
+// (0, rho g, m . g) from the point's state X.
+__device__ __forceinline__ double body_force(const StageArgs &st, const double X[5], int v) {
+  if (!st.force || v == 0) return 0.0;
+  if (v < 4) return X[0] * st.g[v - 1];
+  return X[1] * st.g[0] + X[2] * st.g[1] + X[3] * st.g[2];
 }
-
-// Whether a stage reads the first register (LSRK dU, RK4 accumulator, SSP q2) and the second
-// (RK4 Q).
-__device__ __forceinline__ bool rk_reads_r1(const StageArgs &st) {
-  if (st.mode == kModeLSRK || st.mode == kModeRK4) return !st.first;
-  return st.mode == kModeSSP && (st.stage == 4 || st.stage == 9);
-}
-__device__ __forceinline__ bool rk_reads_r2(const StageArgs &st) { return st.mode == kModeRK4; }
 
 // x: the state the stage was evaluated on; R: its residual; r1, r2: the registers' old values.
 //   LSRK45:   dU <- a dU + dt R; U <- x + b dU                       (out0 = U, reg1 = dU)

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass32(const double *__res
       float acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += ell[c] * sU[slot][v][line_pt<N>(d, c, a, b)];
-      dst[v * NFP] = acc;
+      __builtin_nontemporal_store(acc, &dst[v * NFP]);
     }
     if (VISC) {
 #pragma unroll 5
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass32(const double *__res
         float acc = 0;
 #pragma unroll
         for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][g % NG][line_pt<N>(d, c, a, b)];
-        dst[(5 + g) * NFP] = acc;
+        __builtin_nontemporal_store(acc, &dst[(5 + g) * NFP]);
       }
     }
     double *dm = facem + ((e * 6 + f) * 3) * NFP + kk;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass32(const double *__res
       double acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += elld[c] * sM[slot][i][line_pt<N>(d, c, a, b)];
-      dm[i * NFP] = acc;
+      __builtin_nontemporal_store(acc, &dm[i * NFP]);
     }
   }
 }
@@ -265,10 +265,10 @@ __global__ __launch_bounds__(256) void k_face32(const float *__restrict__ face32
   }
   float *dst = fout32 + (fc * 9) * NFP + kk;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) dst[v * NFP] = 0.5f * (UR[v] - UL[v]);
+  for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(0.5f * (UR[v] - UL[v]), &dst[v * NFP]);
 #pragma unroll
-  for (int v = 1; v < 5; ++v) dst[(4 + v) * NFP] = nm * Fr[v];
-  foutm[fc * NFP + kk] = fc_rho + double(nm * Fr[0]);
+  for (int v = 1; v < 5; ++v) __builtin_nontemporal_store(nm * Fr[v], &dst[(4 + v) * NFP]);
+  __builtin_nontemporal_store(fc_rho + double(nm * Fr[0]), &foutm[fc * NFP + kk]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -399,11 +399,20 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) Fm[d] = jad[d * 3 + 0] * Xd[1] + jad[d * 3 + 1] * Xd[2] + jad[d * 3 + 2] * Xd[3];
-    const bool l1 = rk_reads_r1(st), l2 = rk_reads_r2(st);
+    // (assigned per mode, not initialised up front: a live range from the kernel's start
+    // costs the gradient phase its registers)
+    if (st.mode == kModeLSRK) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      r1[v] = l1 ? reg1[base + v * NS] : 0.0;
-      r2[v] = l2 ? out0[base + v * NS] : 0.0;
+      for (int v = 0; v < 5; ++v) r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+    } else if (st.mode == kModeRK4) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        r1[v] = st.first ? 0.0 : reg1[base + v * NS];
+        r2[v] = out0[base + v * NS];
+      }
+    } else if (st.mode == kModeSSP) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) r1[v] = (st.stage == 4 || st.stage == 9) ? reg1[base + v * NS] : 0.0;
     }
   }
   float div[5] = {0, 0, 0, 0, 0};
@@ -475,9 +484,9 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
   Rv[2] = -double(div[2]) * iJd;
   Rv[3] = -double(div[3]) * iJd;
   Rv[4] = -double(div[4]) * iJd + ref.H_d * Rv[0];
-  add_body_force(st, Xd, Rv);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) rk_store(st, base + v * NS, Xd[v], Rv[v], r1[v], r2[v], out0, reg1, reg2);
+  for (int v = 0; v < 5; ++v)
+    rk_store(st, base + v * NS, Xd[v], Rv[v] + body_force(st, Xd, v), r1[v], r2[v], out0, reg1, reg2);
 }
 
 #define HIPCHK32(call)                                           \
