@@ -46,7 +46,7 @@ def _load():
     L.ora_last_error.restype = ctypes.c_char_p
     L.ora_create.restype = P
     L.ora_create.argtypes = [i32, i32, i64, P, i32, P, f64, f64, f64, f64, i32, i32, i64, P, i32,
-                             ctypes.c_uint64]
+                             ctypes.c_uint64, P, f64]
     L.ora_destroy.argtypes = [P]
     for name in ("ora_residual", "ora_sol_coords"):
         getattr(L, name).argtypes = [P, P] if name == "ora_sol_coords" else [P, P, P]
@@ -89,7 +89,7 @@ class Oracle:
     def __init__(self, mesh, p: int, *, mu: float = 0.0, gamma: float = 1.4,
                  prandtl: float = 0.72, eta: float = 6.0, flux: str = "rusanov",
                  precision: str = "f64", active=None, metric: str = "curl", nthreads: int = 0,
-                 metric_jitter: int = 0):
+                 metric_jitter: int = 0, bc_tag=None, wall_T: float = 1.0):
         L = _load()
         self.p = p
         self.n = p + 1
@@ -107,10 +107,14 @@ class Oracle:
             nact, act_ptr = len(self.active), _ptr(self.active)
             self.NA = nact
         self.nthreads = int(nthreads)
+        tags = None
+        if bc_tag is not None:
+            tags = np.ascontiguousarray(bc_tag, dtype=np.int32)
+            assert tags.shape == (self.E, 6)
         self.h = L.ora_create(PREC[precision], p, self.E, _ptr(self._ev), int(mesh.q),
                               _ptr(self._nodes), gamma, prandtl, mu, eta, FLUX[flux],
                               {"curl": 0, "cross": 1}[metric], nact, act_ptr, self.nthreads,
-                              int(metric_jitter))
+                              int(metric_jitter), _ptr(tags) if tags is not None else None, float(wall_T))
         if not self.h:
             raise RuntimeError("oracle: " + L.ora_last_error().decode())
 

@@ -381,9 +381,10 @@ void face_tangents(int d, int &t1, int &t2) {
 }
 
 struct FaceLink {
-  int64_t nbr = -1;   // neighbour element
+  int64_t nbr = -1;   // neighbour element (-1: a wall)
   int nface = -1;     // neighbour's local face
   bool owner = false; // this side supplies the face normal ("left" side)
+  bool wall = false;  // isothermal no-slip wall (no neighbour)
   vector<int> perm;   // face point k of this side == point perm[k] of the neighbour's face
 };
 
@@ -489,6 +490,8 @@ struct Oracle : Iface {
   vector<T> Xs;    // [slot][3][Ns]     solution point coordinates
   int nthreads;
   T force[3] = {0, 0, 0};  // body force per unit mass (the source term S of Eq. (3))
+  const int32_t *bc_tag = nullptr;  // [E][6] during setup: 1 = isothermal no-slip wall
+  T wall_T = T(1);         // wall temperature p/rho
   int visc_scheme = 0;     // 0 BR2, 1 LDG
   T ldg_tau = T(0.1);      // LDG penalty on the jump of every conserved variable
   vector<T> nut;          // [E] eddy kinematic viscosity per element; empty = none
@@ -512,6 +515,7 @@ struct Oracle : Iface {
   int set_viscous_scheme(int scheme, double tau) override {
     if (scheme != 0 && scheme != 1) { err = "unknown viscous scheme"; return -1; }
     if (scheme == 1 && (int64_t)active.size() != E) { err = "LDG needs the full mesh"; return -1; }
+    if (scheme == 1 && has_walls) { err = "LDG with walls is not supported"; return -1; }
     visc_scheme = scheme;
     ldg_tau = T(tau);
     return 0;
@@ -533,6 +537,8 @@ struct Oracle : Iface {
     if (k == 2) r = std::nextafter(r, -std::numeric_limits<T>::infinity());
     return r;
   }
+
+  bool has_walls = false;
 
   int setup(int p_, int64_t E_, const int64_t *ev, int q, const double *nodes, const Gas<T> &g,
             T eta_, int flux_, int mform, int64_t nact, const int64_t *act, int nth) {
@@ -569,7 +575,15 @@ struct Oracle : Iface {
         faces[key].push_back({e, f});
       }
     for (auto &kv : faces) {
-      if (kv.second.size() != 2) { err = "unpaired face (boundary faces are not supported)"; return -1; }
+      if (kv.second.size() == 1 && bc_tag && bc_tag[kv.second[0].first * 6 + kv.second[0].second] == 1) {
+        // an isothermal no-slip wall: this element owns the face; there is no neighbour
+        FaceLink &lw = links[kv.second[0].first * 6 + kv.second[0].second];
+        lw.nbr = -1; lw.nface = -1; lw.owner = true; lw.wall = true; lw.perm.assign(Nfp, 0);
+        has_walls = true;
+        for (int k = 0; k < Nfp; ++k) lw.perm[k] = k;
+        continue;
+      }
+      if (kv.second.size() != 2) { err = "unpaired face without a wall tag"; return -1; }
       auto A = kv.second[0], Bf = kv.second[1];  // A < B lexicographically (insertion order)
       if (Bf < A) std::swap(A, Bf);
       // corner correspondence: face-local corner (alpha, beta) of A -> vertex id
@@ -622,7 +636,8 @@ struct Oracle : Iface {
     need.assign(E, 0);
     for (int64_t e : active) {
       need[e] = 1;
-      for (int f = 0; f < 6; ++f) need[links[e * 6 + f].nbr] = 1;
+      for (int f = 0; f < 6; ++f)
+        if (!links[e * 6 + f].wall) need[links[e * 6 + f].nbr] = 1;
     }
     slot.assign(E, -1);
     int64_t ns = 0;
@@ -905,6 +920,41 @@ struct Oracle : Iface {
       for (int f = 0; f < 6; ++f) {
         const FaceLink &lk = links[e * 6 + f];
         if (!lk.owner) continue;
+        if (lk.wall) {
+          // isothermal no-slip wall. Inviscid part: the Riemann flux against the mirror state
+          // (rho, -m, E), which is impermeable and carries no energy; viscous part: the wall
+          // state U_w = (rho_L, 0, rho_L T_w / (gamma-1)) as the common state and the one-sided
+          // BR2 gradient G_L + eta r_L with r_L the lifting of U_w - U_L
+          const int64_t sL = slot[e];
+          for (int k = 0; k < Nfp; ++k) {
+            const T *UL = &Uf[((sL * 6 + f) * Nfp + k) * 5];
+            const T *N = &Nf[((sL * 6 + f) * Nfp + k) * 3];
+            T nm = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+            T nh[3] = {N[0] / nm, N[1] / nm, N[2] / nm};
+            T UG[5] = {UL[0], -UL[1], -UL[2], -UL[3], UL[4]};
+            T UW[5] = {UL[0], T(0), T(0), T(0), UL[0] * wall_T / (gas.gamma - 1)};
+            T Fi[5];
+            if (flux == 0) rusanov<T>(UL, UG, nh, gas.gamma, Fi);
+            else roe<T>(UL, UG, nh, gas.gamma, Fi);
+            T Fvn[5] = {0, 0, 0, 0, 0};
+            if (viscous) {
+              const T JL = Jf[(sL * 6 + f) * Nfp + k];
+              T GI[3][5];
+              for (int i = 0; i < 3; ++i)
+                for (int v = 0; v < 5; ++v)
+                  GI[i][v] = Gf[(((sL * 6 + f) * Nfp + k) * 3 + i) * 5 + v] + eta * cl * N[i] / JL * (UW[v] - UL[v]);
+              T Fv[3][5];
+              const T mut = nut.empty() ? T(0) : UW[0] * nut[e];
+              viscous_flux<T>(UW, GI, gas, Fv, mut, prandtl_t);
+              for (int v = 0; v < 5; ++v) Fvn[v] = Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
+            }
+            for (int v = 0; v < 5; ++v) {
+              UCf[((sL * 6 + f) * Nfp + k) * 5 + v] = viscous ? UW[v] : UL[v];
+              FIf[((sL * 6 + f) * Nfp + k) * 5 + v] = nm * (Fi[v] - Fvn[v]);
+            }
+          }
+          continue;
+        }
         const int64_t eR = lk.nbr;
         const int fR = lk.nface;
         // the face is needed if either side is active; stored data exists if both are needed
@@ -1224,9 +1274,11 @@ extern "C" {
 
 const char *ora_last_error() { return g_err.c_str(); }
 
+// bc_tag: [n_elem][6] or NULL; 1 marks an isothermal no-slip wall at temperature wall_T (p/rho)
 void *ora_create(int prec, int p, int64_t n_elem, const int64_t *elem_vert, int q, const double *elem_nodes,
                  double gamma, double prandtl, double mu, double eta, int flux, int metric_form,
-                 int64_t n_active, const int64_t *active, int nthreads, uint64_t metric_jitter) {
+                 int64_t n_active, const int64_t *active, int nthreads, uint64_t metric_jitter,
+                 const int32_t *bc_tag, double wall_T) {
   if (p < 0 || p > 15) { g_err = "p out of range"; return nullptr; }
   if (nthreads <= 0) {
 #ifdef _OPENMP
@@ -1242,7 +1294,10 @@ void *ora_create(int prec, int p, int64_t n_elem, const int64_t *elem_vert, int 
     using T = decltype(tag);
     Gas<T> g{T(gamma), T(prandtl), T(mu)};
     o->jitter = metric_jitter;
+    o->bc_tag = bc_tag;
+    o->wall_T = T(wall_T);
     rc = o->setup(p, n_elem, elem_vert, q, elem_nodes, g, T(eta), flux, metric_form, n_active, active, nthreads);
+    o->bc_tag = nullptr;  // borrowed for the setup only
     e = o->err;
     h = o;
   };

@@ -228,6 +228,24 @@ def random_smooth_perturbation(xyz_e3s: np.ndarray, seed: int, amp: float = 1e-3
     return points_to_state_layout(amp * out)
 
 
+def boundary_tags(mesh: Mesh, tag: int = 1) -> np.ndarray:
+    """[E][6] int32: `tag` on every face whose sorted corner ids occur once in the mesh (a
+    physical boundary), 0 elsewhere. Local face f lies at reference coordinate f//2 = -1 (even
+    f) or +1 (odd f), with the VTK corner order."""
+    E = mesh.elem_vert.shape[0]
+    keys = {}
+    for e in range(E):
+        for f in range(6):
+            d, s = f // 2, f % 2
+            ids = tuple(sorted(int(mesh.elem_vert[e, c]) for c in range(8) if VTK_CORNERS[c][d] == s))
+            keys.setdefault(ids, []).append((e, f))
+    out = np.zeros((E, 6), dtype=np.int32)
+    for lst in keys.values():
+        if len(lst) == 1:
+            out[lst[0]] = tag
+    return out
+
+
 def box_axis_points(mesh: Mesh, p: int):
     """The distinct solution-point coordinates along each axis of an uncurved box mesh: for
     axis d, n_d (p+1) values ordered (element index, point index)."""
