@@ -72,9 +72,9 @@ enum fr_scheme {                                  /* explicit Runge-Kutta scheme
  *   q          degree of the geometry, 1..max(p,1); the mesh is isoparametric when q == p.
  *   n_elem     number of hexahedra.
  *   elem_vert  [n_elem][8] corner vertex ids in VTK hexahedron order. Faces are paired by
- *              their sorted corner ids, so periodic images must share one id; every face must
- *              pair (no physical boundaries in this build), which needs >= 3 elements across
- *              a periodic direction.
+ *              their sorted corner ids, so periodic images must share one id (which needs >= 3
+ *              elements across a periodic direction); a face that does not pair must be a
+ *              tagged wall (bc_tag).
  *   elem_nodes [n_elem][(q+1)^3][3] node coordinates at the tensor Gauss-Lobatto-Legendre
  *              points of degree q, reference index i + (q+1)*(j + (q+1)*k).
  *   gamma, prandtl   ratio of specific heats and Prandtl number.
@@ -83,6 +83,12 @@ enum fr_scheme {                                  /* explicit Runge-Kutta scheme
  *   viscous    enum fr_viscous: the common viscous flux (0 = BR2; zero-initialised descriptors
  *              keep it). FR_LDG needs prec = FR_FP64 (FR_ERR_UNSUPPORTED otherwise).
  *   ldg_tau    LDG penalty (>= 0) on the jump of every conserved variable.
+ *   bc_tag     [n_elem][6] or NULL. A face that does not pair must carry tag 1: an isothermal
+ *              no-slip wall at temperature wall_T (p/rho, > 0). Its inviscid flux is the Riemann
+ *              flux against the mirror state (rho, -m, E) (impermeable, no energy flux); its
+ *              viscous flux uses the wall state (rho, 0, rho wall_T/(gamma-1)) as the common
+ *              state and the one-sided BR2 gradient. Walls need prec = FR_FP64 and FR_BR2
+ *              (FR_ERR_UNSUPPORTED otherwise).
  *   flux       enum fr_flux.   prec: enum fr_prec.
  *   check_finite  non-zero: fr_residual scans its result and reports FR_ERR_NONFINITE.
  *   ref_rho, ref_p  reference state at rest used by FR_FP32 (ignored by FR_FP64): the FP32
@@ -107,6 +113,8 @@ typedef struct {
   double ref_rho;
   double ref_p;
   double ldg_tau;
+  const int32_t *bc_tag;
+  double wall_T;
 } fr_mesh_desc;
 
 /* Build a mesh on the current HIP device: pair faces (sort-and-match on corner ids, as the
@@ -129,6 +137,21 @@ int fr_sol_coords(fr_mesh_t m, double *xyz);
 /* Copy a state [n_elem][5][N_s] into / out of the handle (see on_device above). */
 int fr_set_state(fr_mesh_t m, const double *U, int on_device);
 int fr_get_state(fr_mesh_t m, double *U, int on_device);
+
+/* Tile shapes of the FP64 stage kernels, chosen by the autotuner or by the caller:
+ *   epb  elements per block of the element kernels (pre-pass, volume): 0 = 256/N_s (at least
+ *        one), 1 = half of that (at least one);
+ *   fbs  threads per block of the face kernel: 0 = 256, 1 = 128, 2 = 64.
+ * Results are bitwise independent of the tiles (every thread does the same arithmetic). The
+ * FP32 form keeps its default tiles. A batch captures the tiles in force at its creation. */
+int fr_set_tiles(fr_mesh_t m, int32_t epb, int32_t fbs);
+int fr_get_tiles(fr_mesh_t m, int32_t *epb, int32_t *fbs);
+
+/* Autotuner: time each of the 6 tile choices on this mesh and state with n_trials residual
+ * stages (HIP events on the handle's stream, after one warm-up stage each) and keep the fastest.
+ * ms (may be NULL) receives the mean ms per stage of (epb, fbs) = (0,0), (0,1), (0,2), (1,0),
+ * (1,1), (1,2). Allocates a scratch residual for the call; waits. The FP32 form returns zeros. */
+int fr_autotune(fr_mesh_t m, int n_trials, double *ms);
 
 /* Source term S of Eq. (3) as a constant body force per unit mass g[3] ("body forcing" is
  * among the solver's physical models, section "ZFR Framework"): S = (0, rho g, m . g), added
@@ -164,14 +187,16 @@ int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *m
 
 /* Host-only: run the mesh setup of fr_mesh_create without a GPU and return its arrays, for
  * inspection. Faces are numbered in owner order (the owner of a face is the side with the
- * smaller element index, then the smaller local face); a fully paired mesh has 3 n_elem.
+ * smaller element index, then the smaller local face; a wall's element owns it); there are
+ * F = 3 n_elem + n_wall/2 faces (n_wall tagged wall faces).
  *   geo  [n_elem][10][N_s]: rows |J| dxi_n/dx_i (n-major, 9) then 1/|J|;
- *   fgeo [3 n_elem][4][N_fp]: the owner's outward scaled normal (3) and the BR2 factor
- *        sigma = eta (p+1)^2/8 (1/|J|_L + 1/|J|_R) at each owner face point;
- *   ftab [3 n_elem][4]: owner element, other element, code (bits 0-2 owner's face, 3-5 other
- *        face, 6 swap, 7 flip u, 8 flip v: the owner point -> other point map), 0;
- *   conn [n_elem][6][2]: neighbour element and packed code (bits 0-2 neighbour face, 3 swap,
- *        4 flip u, 5 flip v, 6 this side owns the face);
+ *   fgeo [F][4][N_fp]: the owner's outward scaled normal (3) and the BR2 factor
+ *        sigma = eta (p+1)^2/8 (1/|J|_L + 1/|J|_R) at each owner face point (2/|J|_L at a wall);
+ *   ftab [F][4]: owner element, other element (-1 at a wall), code (bits 0-2 owner's face, 3-5
+ *        other face, 6 swap, 7 flip u, 8 flip v: the owner point -> other point map; bit 9 a
+ *        wall), 0;
+ *   conn [n_elem][6][2]: neighbour element (-1 at a wall) and packed code (bits 0-2 neighbour
+ *        face, 3 swap, 4 flip u, 5 flip v, 6 this side owns the face, 7 a wall);
  *   xyz  [n_elem][3][N_s] solution-point coordinates.
  * Point (a, b) maps to (u', v') with (u, v) = swap ? (b, a) : (a, b), u' = flip_u ? p-u : u,
  * v' = flip_v ? p-v : v. Any output pointer may be NULL. Errors: FR_ERR_ARG, FR_ERR_MESH. */

@@ -5,8 +5,9 @@ Workload (seeded with numpy.random.default_rng(seed)): n_mesh periodic box meshe
 per direction), degree p uniform in {2, 3, 4, 5}, a uniform flow at Mach 0.2 to 0.5 (|u| = 1)
 with a seeded smooth random perturbation, Roe + BR2 at mu = 1e-4, the FP32 form (FP32 operators
 and fluxes, FP64 state and mass equation) and LSRK45 with dt from the stability estimate
-dt = 1.5 h / ((|u| + c)(p + 1)(p + 2) 1.7). The meshes are fully periodic: walls are not part
-of this build, so the channel's isothermal walls are replaced by periodicity in y.
+dt = 1.5 h / ((|u| + c)(p + 1)(p + 2) 1.7). By default the meshes are fully periodic; with
+--walls they are channels, periodic in x and z with isothermal no-slip walls in y at the flow's
+temperature (the flow then runs along x), in FP64 (walls need the FP64 path).
 
 Two ways to run the same steps are timed on the same meshes and state:
   sequential  fr_rk_step on each mesh in turn (15 kernel launches per mesh and step),
@@ -46,18 +47,24 @@ def stable_dt(n: int, p: int, mach: float) -> float:
     return 1.5 * h / ((1.0 + c) * (p + 1) * (p + 2) * 1.7)
 
 
-def build(fr, spec):
-    m = I.box_mesh(spec["n"], q=1)
+def build(fr, spec, walls=False):
     p0 = 1.0 / (GAMMA * spec["mach"] ** 2)
-    g = fr.FRMesh(m, spec["p"], mu=MU, flux="roe", prec="fp32", ref_rho=1.0, ref_p=p0)
-    X = g.sol_coords()
-    U = I.state_from_coords(X, I.freestream_state, mach=spec["mach"])
+    if walls:
+        m = I.box_mesh(spec["n"], q=1, periodic=(True, False, True))
+        g = fr.FRMesh(m, spec["p"], mu=MU, flux="roe", bc_tag=I.boundary_tags(m), wall_T=p0)
+        X = g.sol_coords()
+        U = I.state_from_coords(X, I.freestream_state, mach=spec["mach"], direction=(1.0, 0.0, 0.0))
+    else:
+        m = I.box_mesh(spec["n"], q=1)
+        g = fr.FRMesh(m, spec["p"], mu=MU, flux="roe", prec="fp32", ref_rho=1.0, ref_p=p0)
+        X = g.sol_coords()
+        U = I.state_from_coords(X, I.freestream_state, mach=spec["mach"])
     U += I.random_smooth_perturbation(X, seed=spec["seed"], amp=0.01)
     g.set_state(U)
     return g, U
 
 
-def run(n_mesh=48, steps=10, warmup=2, seed=0):
+def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=False):
     import torch
 
     from . import fr
@@ -67,7 +74,7 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0):
     t0 = time.time()
     meshes, states, dts = [], [], []
     for s in specs:
-        g, U = build(fr, s)
+        g, U = build(fr, s, walls)
         meshes.append(g)
         states.append(U)
         dts.append(stable_dt(s["n"], s["p"], s["mach"]))
@@ -112,8 +119,9 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0):
     for g in meshes:
         g.close()
     out = {
-        "workload": f"{n_mesh} periodic box meshes, log-uniform 8^3..40^3 elements, p in 2..5, Mach 0.2-0.5, "
-                    f"Roe+BR2 mu={MU}, FP32 form, LSRK45, seed {seed}",
+        "workload": f"{n_mesh} {'channel meshes (isothermal walls in y)' if walls else 'periodic box meshes'}, "
+                    f"log-uniform 8^3..40^3 elements, p in 2..5, Mach 0.2-0.5, Roe+BR2 mu={MU}, "
+                    f"{'FP64' if walls else 'FP32 form'}, LSRK45, seed {seed}",
         "n_mesh": n_mesh, "dof": int(dof), "elements": int(sum(g.E for g in meshes)),
         "steps": steps, "stages_per_step": stages,
         "sequential": {"ms_per_step": ms_seq, "dof_updates_per_s": dof * stages / (ms_seq * 1e-3)},
@@ -132,9 +140,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--walls", action="store_true")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = run(a.n_mesh, a.steps, a.warmup, a.seed)
+    res = run(a.n_mesh, a.steps, a.warmup, a.seed, a.walls)
     line = {k: v for k, v in res.items() if k != "meshes"}
     print(json.dumps(line), flush=True)
     if a.out:

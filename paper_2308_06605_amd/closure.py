@@ -414,7 +414,7 @@ def evaluate(model_path, ref_path, out=None):
             sl = spectrum(states[t_end], (COARSE[0],) * 3, COARSE[1])
             kmax = COARSE[0] * (COARSE[1] + 1) // 3  # compare up to a third of the grid's wavenumbers
             a, b = sl[1:kmax + 1], sr[1:kmax + 1]
-            ok = (a > 0) & (b > 0)
+            ok = (b > 1e-10 * sr.max()) & (a > 0)  # wavenumbers that carry energy
             res[name]["spectrum_rel_err"] = float(np.sqrt(np.mean((np.log(a[ok]) - np.log(b[ok])) ** 2)))
             res[name]["spectrum"] = sl[: kmax + 1].tolist()
             res["spectrum_ref"] = sr[: kmax + 1].tolist()

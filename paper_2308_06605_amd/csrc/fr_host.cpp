@@ -280,7 +280,7 @@ struct Topology {
 };
 
 // Returns "" on success or an error message.
-static std::string pair_faces(int64_t E, const int64_t *ev, int p, Topology &T) {
+static std::string pair_faces(int64_t E, const int64_t *ev, const int32_t *bc_tag, int p, Topology &T) {
   const int n = p + 1, Nfp = n * n;
   T.conn.assign(E * 6, frk::FaceConn{-1, 0});
   T.perm.assign(E * 6 * Nfp, -1);
@@ -360,10 +360,15 @@ static std::string pair_faces(int64_t E, const int64_t *ev, int p, Topology &T) 
       if (!err.empty()) return err;
     }
   }
-  if (!open.empty()) {
-    int64_t a = open.begin()->second;
-    return "unpaired face: element " + std::to_string(a / 6) + " face " + std::to_string(a % 6) +
-           " (every face must pair; physical boundaries are not supported)";
+  // unpaired faces: isothermal no-slip walls where tagged (owned by their element, no
+  // neighbour, identity point map), an error otherwise
+  for (const auto &kv : open) {
+    const int64_t a = kv.second;
+    if (!bc_tag || bc_tag[a] != 1)
+      return "unpaired face: element " + std::to_string(a / 6) + " face " + std::to_string(a % 6) +
+             " (every face must pair or be tagged as a wall)";
+    T.conn[a] = frk::FaceConn{-1, (int32_t)(64 | 128)};
+    for (int k = 0; k < Nfp; ++k) T.perm[a * Nfp + k] = k;
   }
   return "";
 }
@@ -535,8 +540,8 @@ SgsOps sgs_ops(int p) {
   return o;
 }
 
-std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const double *nodes, double eta,
-                            HostMesh &H) {
+std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const double *nodes, const int32_t *bc_tag,
+                            double eta, HostMesh &H) {
   using frh::LD;
   H.p = p;
   H.q = q;
@@ -545,7 +550,7 @@ std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const do
   frh::Basis B = frh::make_basis(p);
   H.ops = basis_ops(p);
   frh::Topology T;
-  std::string err = frh::pair_faces(E, ev, p, T);
+  std::string err = frh::pair_faces(E, ev, bc_tag, p, T);
   if (!err.empty()) return err;
 
   frh::Geometry G;
@@ -585,6 +590,12 @@ std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const do
       const FaceConn c = T.conn[e * 6 + f];
       if (!((c.code >> 6) & 1)) continue;
       const int32_t fid = (int32_t)H.ftab.size();
+      if (c.nbr < 0) {  // a wall: no other side
+        H.ftab.push_back(FaceRec{(int32_t)e, -1, f | kFaceWall, 0});
+        H.fref[e * 6 + f] = FaceRef{fid, 64};
+        ++H.n_wall;
+        continue;
+      }
       const int fn = c.code & 7;
       FaceRec r;
       r.eL = (int32_t)e;
@@ -604,9 +615,14 @@ std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const do
     const int fL = r.code & 7, fR = (r.code >> 3) & 7;
     double *dst = &H.fgeo[(size_t)fid * 4 * Nfp];
     for (int k = 0; k < Nfp; ++k) {
-      const int kr = T.perm[((size_t)r.eL * 6 + fL) * Nfp + k];
       for (int i = 0; i < 3; ++i) dst[i * Nfp + k] = (double)G.nface[(((size_t)r.eL * 6 + fL) * Nfp + k) * 3 + i];
       const double jl = (double)G.jface[((size_t)r.eL * 6 + fL) * Nfp + k];
+      if (r.eR < 0) {
+        // wall: the one-sided lifting, as if the other side's |J| equalled this side's
+        dst[3 * Nfp + k] = (double)((LD)eta * cl * (2.0L / (LD)jl) / 4);
+        continue;
+      }
+      const int kr = T.perm[((size_t)r.eL * 6 + fL) * Nfp + k];
       const double jr = (double)G.jface[((size_t)r.eR * 6 + fR) * Nfp + kr];
       dst[3 * Nfp + k] = (double)((LD)eta * cl * (1.0L / (LD)jl + 1.0L / (LD)jr) / 4);
     }

@@ -66,7 +66,9 @@ struct Physics {
 
 // One face (owner side "L", other side "R"), the unit of the face kernel.
 //   eL, eR : elements; code: bits 0-2 L's local face, 3-5 R's local face, 6 swap, 7 flip u,
-//   8 flip v -- the map from L's face point (a, b) to R's point, as in FaceConn.
+//   8 flip v -- the map from L's face point (a, b) to R's point, as in FaceConn; bit 9
+//   (kFaceWall) an isothermal no-slip wall, with eR = -1.
+constexpr int32_t kFaceWall = 1 << 9;
 struct FaceRec {
   int32_t eL;
   int32_t eR;
@@ -125,6 +127,10 @@ struct DeviceMesh {
   void *fout32 = nullptr;   // [F][9][Nfp] float: J (5), owner's momentum flux (3), reduced energy flux
   void *foutm = nullptr;    // [F][Nfp] double: owner's mass flux
   double ref_rho = 1.0, ref_p = 0.0;
+  int tile_epb = 0;             // element kernels: 0 = 256/Ns elements per block, 1 = half
+  int tile_fbs = 0;             // face kernel block: 0 = 256, 1 = 128, 2 = 64 threads
+  bool walls = false;           // isothermal no-slip wall faces present
+  double wall_T = 1.0;          // their temperature p/rho
   bool ldg = false;             // LDG common viscous flux (else BR2)
   double ldg_tau = 0.0;
   double force[3] = {0, 0, 0};  // body force per unit mass (source term S)
@@ -146,6 +152,7 @@ struct DeviceMesh {
 struct HostMesh {
   int p = 0, q = 1;
   int64_t E = 0;
+  int64_t n_wall = 0;          // wall faces
   Ops1D ops;
   std::vector<double> geo;     // [E][10][Ns]
   std::vector<double> fgeo;    // [F][4][Nfp]
@@ -175,6 +182,6 @@ int mlp_forward_nu(fr_mlp_s *m, const float *X, int64_t n, int64_t ldx, double *
 
 // Returns "" on success or a message naming the offending element / face.
 std::string build_host_mesh(int p, int q, int64_t E, const int64_t *elem_vert, const double *elem_nodes,
-                            double br2_eta, HostMesh &H);
+                            const int32_t *bc_tag, double br2_eta, HostMesh &H);
 
 }  // namespace frk

@@ -39,13 +39,13 @@ using namespace frk;
 // ------------------------------------------------------------------------------------------
 // K1: element pre-pass
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC>
-__global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void k_prepass(const double *__restrict__ X,
+template <int P, typename real, bool VISC, int EPBX>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void k_prepass(const double *__restrict__ X,
                                                            const real *__restrict__ geo,
                                                            real *__restrict__ face, int64_t E,
                                                            OpsT<real> ops) {
   using C = Cfg<P>;
-  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int NG = VISC ? 15 : 0;
   __shared__ real sU[EPB][5][NS];
   __shared__ real sG[EPB][NG > 0 ? NG : 1][NS];
@@ -114,18 +114,74 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void 
 // Writes J = (U_R - U_L)/2 = U^C - U_L and the owner's transformed common normal flux
 // F^{I,perp}_L = |N| (F*_inv - F_v(U^C, G^I) . n) to a face-major buffer [F][10][Nfp].
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC, bool SGS, bool LDG>
-__global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
+// Isothermal no-slip wall (face record with kFaceWall, no other side). Inviscid part: the
+// Riemann flux against the mirror state (rho, -m, E), impermeable and without energy flux.
+// Viscous part: the wall state U_w = (rho_L, 0, rho_L T_w/(gamma-1)) as the common state and the
+// one-sided BR2 gradient G_L + 2 sigma N (U_w - U_L) (sigma of a wall face is one-sided).
+template <typename real, bool VISC, bool SGS>
+__device__ __forceinline__ void wall_face(const real *srcL, const real *fg, int NFP, int64_t eL, const Phys<real> &ph,
+                                          int flux, const double *nut, real kt, real tw_gm1, real *dst) {
+  real UL[5], UG[5], UW[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) UL[v] = srcL[v * NFP];
+  UG[0] = UL[0];
+  UG[1] = -UL[1];
+  UG[2] = -UL[2];
+  UG[3] = -UL[3];
+  UG[4] = UL[4];
+  UW[0] = UL[0];
+  UW[1] = UW[2] = UW[3] = real(0);
+  UW[4] = UL[0] * tw_gm1;
+  const real NL[3] = {fg[0], fg[NFP], fg[2 * NFP]};
+  const real nm = sqrt(NL[0] * NL[0] + NL[1] * NL[1] + NL[2] * NL[2]);
+  const real inm = real(1) / nm;
+  const real nh[3] = {NL[0] * inm, NL[1] * inm, NL[2] * inm};
+  real Fi[5];
+  if (flux == 0) rusanov(UL, UG, nh, ph, Fi);
+  else roe(UL, UG, nh, ph, Fi);
+  real Fvn[5] = {0, 0, 0, 0, 0};
+  if (VISC) {
+    const real sig2 = real(2) * fg[3 * NFP];
+    real GI[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) GI[i][v] = srcL[(5 + i * 5 + v) * NFP] + sig2 * NL[i] * (UW[v] - UL[v]);
+    real mu = ph.mu, kap = ph.kappa;
+    if (SGS) {
+      const real mut = UW[0] * real(nut[eL]);
+      mu += mut;
+      kap += mut * kt;
+    }
+    real Fv[3][5];
+    visc_flux_mk(UW, GI, ph.gm1, mu, kap, Fv);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Fvn[v] = Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    __builtin_nontemporal_store(VISC ? UW[v] - UL[v] : real(0), &dst[v * NFP]);
+    __builtin_nontemporal_store(nm * (Fi[v] - Fvn[v]), &dst[(5 + v) * NFP]);
+  }
+}
+
+template <int P, typename real, bool VISC, bool SGS, bool LDG, int FBS>
+__global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
                                               const FaceRec *__restrict__ ftab, int64_t F, Phys<real> ph,
                                               int flux, real *__restrict__ fout, const double *__restrict__ nut,
-                                              real kt, real tau) {
+                                              real kt, real tau, real tw_gm1) {
   constexpr int N = P + 1, NFP = N * N;
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * FBS + threadIdx.x;
   const int64_t fc = gid / NFP;
   if (fc >= F) return;
   const int kk = (int)(gid - fc * NFP);
   const FaceRec r = ftab[fc];
   const int fL = r.code & 7, fR = (r.code >> 3) & 7;
+  if (!LDG && (r.code & kFaceWall)) {
+    wall_face<real, VISC, SGS>(face + (((int64_t)r.eL * 6 + fL) * 20) * NFP + kk, fgeo + (fc * 4) * NFP + kk, NFP,
+                               r.eL, ph, flux, nut, kt, tw_gm1, fout + (fc * 10) * NFP + kk);
+    return;
+  }
   const bool swp = (r.code >> 6) & 1, flu = (r.code >> 7) & 1, flv = (r.code >> 8) & 1;
   const int a = kk % N, b = kk / N;
   const int uu = swp ? b : a, vv = swp ? a : b;
@@ -206,14 +262,14 @@ __global__ __launch_bounds__(256) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 // transformed divergence sum_n D_n F^n plus the flux correction
 // (s F^{I,perp} - F^d_f) g'(xi_d), R = -div/|J|, and the RK register update.
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC, bool SGS, bool LDG>
-__global__ __launch_bounds__(Cfg<P>::BLOCK) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k_volume(
+template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k_volume(
     const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
     double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2,
     const double *__restrict__ nut, real kt) {
   using C = Cfg<P>;
-  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int NJ = (VISC ? 10 : 5) * NF;
   __shared__ real sUall[EPB][5 * NS];  // state, then the transformed flux of one direction
   __shared__ real sJall[EPB][NJ];      // [5][NF] flux along +xi_d (then its jump); [5][NF] U^C - U
@@ -736,7 +792,7 @@ static int features(DeviceMesh &dm, const double *X, float *feat) {
   }
 }
 
-template <int P, typename real, bool VISC, bool SGS, bool LDG>
+template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX, int FBS>
 static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
                           double *ms) {
   using C = Cfg<P>;
@@ -751,32 +807,32 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
   Phys<real> ph{real(dm.phys.gamma), real(dm.phys.gamma - 1.0), real(dm.phys.mu), real(dm.phys.kappa)};
   // heat-flux coefficient per unit eddy viscosity: gamma / ((gamma - 1) Pr_t)
   const real kt = real(dm.phys.gamma / ((dm.phys.gamma - 1.0) * dm.prandtl_t));
-  const int64_t blocks = (dm.E + C::EPB - 1) / C::EPB;
-  const int64_t fblocks = (dm.F * C::NFP + 255) / 256;
+  const int64_t blocks = (dm.E + EPBX - 1) / EPBX;
+  const int64_t fblocks = (dm.F * C::NFP + FBS - 1) / FBS;
   hipStream_t s = (hipStream_t)dm.stream;
   hipEvent_t ev[4];
   if (ms) {
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], s));
   }
-  hipLaunchKernelGGL((k_prepass<P, real, VISC && !LDG>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+  hipLaunchKernelGGL((k_prepass<P, real, VISC && !LDG, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
                      (const real *)dm.geo, (real *)dm.face, dm.E, ops);
   HIPCHK(hipGetLastError());
   if (LDG) {
     static_assert(sizeof(OpsT<double>) == sizeof(Ops1D), "operator tables share one layout");
     OpsT<double> od;
     std::memcpy(&od, &dm.ops, sizeof od);
-    hipLaunchKernelGGL((k_ldg_grad<P>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X, (const double *)dm.geo,
-                       dm.fref, dm.ftab, (double *)dm.face, dm.E, od);
+    hipLaunchKernelGGL((k_ldg_grad<P>), dim3((unsigned)((dm.E + C::EPB - 1) / C::EPB)), dim3(C::BLOCK), 0, s, X,
+                       (const double *)dm.geo, dm.fref, dm.ftab, (double *)dm.face, dm.E, od);
     HIPCHK(hipGetLastError());
   }
   if (ms) HIPCHK(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL((k_face<P, real, VISC, SGS, LDG>), dim3((unsigned)fblocks), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_face<P, real, VISC, SGS, LDG, FBS>), dim3((unsigned)fblocks), dim3(FBS), 0, s,
                      (const real *)dm.face, (const real *)dm.fgeo, dm.ftab, dm.F, ph, dm.flux, (real *)dm.fout,
-                     dm.nut, kt, real(dm.ldg_tau));
+                     dm.nut, kt, real(dm.ldg_tau), real(dm.wall_T / (dm.phys.gamma - 1.0)));
   HIPCHK(hipGetLastError());
   if (ms) HIPCHK(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL((k_volume<P, real, VISC, SGS, LDG>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X,
+  hipLaunchKernelGGL((k_volume<P, real, VISC, SGS, LDG, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
                      (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1, reg2,
                      dm.nut, kt);
   HIPCHK(hipGetLastError());
@@ -793,18 +849,35 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
   return FR_OK;
 }
 
+// The tile shapes (the autotuner's choice, DeviceMesh::tile_epb / tile_fbs): elements per block
+// of the element kernels, 256/N_s or half of it, and the face kernel's block of 256, 128 or 64
+// threads. Every thread's arithmetic is the same whatever the tiles.
+template <int P, typename real, bool VISC, bool SGS, bool LDG>
+static int launch_stage_tiles(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
+                              double *ms) {
+  constexpr int E0 = Cfg<P>::EPB, E1 = E0 > 1 ? E0 / 2 : 1;
+  if (dm.tile_epb == 0) {
+    if (dm.tile_fbs == 0) return launch_stage_t<P, real, VISC, SGS, LDG, E0, 256>(dm, X, st, o, r1, r2, ms);
+    if (dm.tile_fbs == 1) return launch_stage_t<P, real, VISC, SGS, LDG, E0, 128>(dm, X, st, o, r1, r2, ms);
+    return launch_stage_t<P, real, VISC, SGS, LDG, E0, 64>(dm, X, st, o, r1, r2, ms);
+  }
+  if (dm.tile_fbs == 0) return launch_stage_t<P, real, VISC, SGS, LDG, E1, 256>(dm, X, st, o, r1, r2, ms);
+  if (dm.tile_fbs == 1) return launch_stage_t<P, real, VISC, SGS, LDG, E1, 128>(dm, X, st, o, r1, r2, ms);
+  return launch_stage_t<P, real, VISC, SGS, LDG, E1, 64>(dm, X, st, o, r1, r2, ms);
+}
+
 template <typename real, bool VISC, bool SGS, bool LDG>
 static int launch_stage_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
                           double *ms) {
   switch (dm.p) {
-    case 0: return launch_stage_t<0, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
-    case 1: return launch_stage_t<1, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
-    case 2: return launch_stage_t<2, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
-    case 3: return launch_stage_t<3, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
-    case 4: return launch_stage_t<4, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
-    case 5: return launch_stage_t<5, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
-    case 6: return launch_stage_t<6, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
-    case 7: return launch_stage_t<7, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 0: return launch_stage_tiles<0, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 1: return launch_stage_tiles<1, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 2: return launch_stage_tiles<2, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 3: return launch_stage_tiles<3, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 4: return launch_stage_tiles<4, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 5: return launch_stage_tiles<5, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 6: return launch_stage_tiles<6, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
+    case 7: return launch_stage_tiles<7, real, VISC, SGS, LDG>(dm, X, st, o, r1, r2, ms);
     default: return fail(FR_ERR_UNSUPPORTED, "p out of range");
   }
 }
@@ -950,8 +1023,13 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
     return fail(FR_ERR_ARG, "ldg_tau must be finite and >= 0");
 
   HostMesh H;
-  std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->br2_eta, H);
+  std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->bc_tag, d->br2_eta, H);
   if (!err.empty()) return fail(FR_ERR_MESH, err);
+  if (H.n_wall > 0) {
+    if (d->prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "walls need prec = FR_FP64");
+    if (d->viscous == FR_LDG) return fail(FR_ERR_UNSUPPORTED, "walls need the BR2 viscous flux");
+    if (!(d->wall_T > 0.0) || !std::isfinite(d->wall_T)) return fail(FR_ERR_ARG, "wall_T must be finite and > 0");
+  }
 
   fr_mesh_s *m = new fr_mesh_s();
   m->magic = kMagic;
@@ -967,6 +1045,8 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   dm.eta = d->br2_eta;
   dm.ldg = d->viscous == FR_LDG;
   dm.ldg_tau = dm.ldg ? d->ldg_tau : 0.0;
+  dm.walls = H.n_wall > 0;
+  dm.wall_T = dm.walls ? d->wall_T : 1.0;
   dm.phys = Physics{d->gamma, d->prandtl, d->mu, d->mu * d->gamma / (d->prandtl * (d->gamma - 1.0))};
   dm.ops = H.ops;
   dm.sgs_ops = sgs_ops(d->p);
@@ -1034,10 +1114,10 @@ int fr_mesh_geometry_host(const fr_mesh_desc *d, double *geo, double *fgeo, int3
   if (d->q < 1 || d->q > (d->p > 1 ? d->p : 1)) return fail(FR_ERR_ARG, "q must be in 1..max(p,1)");
   if (d->n_elem <= 0 || d->n_elem > (int64_t)INT32_MAX) return fail(FR_ERR_ARG, "n_elem out of range");
   HostMesh H;
-  std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->br2_eta, H);
+  std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->bc_tag, d->br2_eta, H);
   if (!err.empty()) return fail(FR_ERR_MESH, err);
   if (geo) std::memcpy(geo, H.geo.data(), H.geo.size() * sizeof(double));
-  if (H.ftab.size() != (size_t)d->n_elem * 3) return fail(FR_ERR_MESH, "face count is not 3 n_elem");
+  if (H.ftab.size() != (size_t)(d->n_elem * 3 + H.n_wall / 2)) return fail(FR_ERR_MESH, "unexpected face count");
   if (fgeo) std::memcpy(fgeo, H.fgeo.data(), H.fgeo.size() * sizeof(double));
   if (ftab) std::memcpy(ftab, H.ftab.data(), H.ftab.size() * sizeof(FaceRec));
   if (conn) std::memcpy(conn, H.conn.data(), H.conn.size() * sizeof(FaceConn));
@@ -1201,6 +1281,67 @@ int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_b
   if (n_sol) *n_sol = m->dm.Ns;
   if (device_bytes) *device_bytes = m->dm.bytes;
   return FR_OK;
+}
+
+int fr_set_tiles(fr_mesh_t m, int32_t epb, int32_t fbs) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (epb < 0 || epb > 1 || fbs < 0 || fbs > 2) return fail(FR_ERR_ARG, "epb must be 0..1 and fbs 0..2");
+  m->dm.tile_epb = epb;
+  m->dm.tile_fbs = fbs;
+  return FR_OK;
+}
+
+int fr_get_tiles(fr_mesh_t m, int32_t *epb, int32_t *fbs) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (epb) *epb = m->dm.tile_epb;
+  if (fbs) *fbs = m->dm.tile_fbs;
+  return FR_OK;
+}
+
+int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (n_trials < 1) return fail(FR_ERR_ARG, "n_trials must be >= 1");
+  DeviceMesh &dm = m->dm;
+  if (dm.prec != FR_FP64) {  // the FP32 form keeps its default tiles
+    if (ms)
+      for (int i = 0; i < 6; ++i) ms[i] = 0.0;
+    return FR_OK;
+  }
+  const int64_t M = dm.E * 5 * dm.Ns;
+  double *tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, M * sizeof(double)));
+  hipStream_t s = (hipStream_t)dm.stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = FR_OK;
+  double best = 1e300, t[6];
+  int bi = 0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FR_ERR_HIP, "hipEventCreate");
+  StageArgs st{};
+  st.mode = kModeResidual;
+  for (int c = 0; c < 6 && rc == FR_OK; ++c) {
+    dm.tile_epb = c / 3;
+    dm.tile_fbs = c % 3;
+    rc = launch_stage(dm, dm.U, st, tmp, nullptr, nullptr);  // warm-up
+    if (rc == FR_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(FR_ERR_HIP, "hipEventRecord");
+    for (int k = 0; k < n_trials && rc == FR_OK; ++k) rc = launch_stage(dm, dm.U, st, tmp, nullptr, nullptr);
+    float el = 0;
+    if (rc == FR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&el, e0, e1) != hipSuccess))
+      rc = fail(FR_ERR_HIP, "timing the tile choices");
+    t[c] = el / n_trials;
+    if (rc == FR_OK && t[c] < best) {
+      best = t[c];
+      bi = c;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(tmp);
+  dm.tile_epb = bi / 3;
+  dm.tile_fbs = bi % 3;
+  if (rc == FR_OK && ms)
+    for (int i = 0; i < 6; ++i) ms[i] = t[i];
+  return rc;
 }
 
 int fr_set_body_force(fr_mesh_t m, const double *g) {

@@ -37,6 +37,7 @@ class fr_mesh_desc(ctypes.Structure):
         ("br2_eta", ctypes.c_double), ("flux", ctypes.c_int32), ("prec", ctypes.c_int32),
         ("check_finite", ctypes.c_int32), ("viscous", ctypes.c_int32),
         ("ref_rho", ctypes.c_double), ("ref_p", ctypes.c_double), ("ldg_tau", ctypes.c_double),
+        ("bc_tag", ctypes.c_void_p), ("wall_T", ctypes.c_double),
     ]
 
 
@@ -74,6 +75,9 @@ def load():
     L.fr_basis_host.argtypes = [i32, P, P, P, P, P]
     L.fr_kinetic_energy.argtypes = [P, P]
     L.fr_set_body_force.argtypes = [P, P]
+    L.fr_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    L.fr_get_tiles.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.fr_autotune.argtypes = [P, i32, P]
     L.fr_batch_create.argtypes = [P, ctypes.c_int32, P, i32, P, ctypes.POINTER(P)]
     L.fr_batch_step.argtypes = [P, i32]
     L.fr_batch_set_stream.argtypes = [P, P]
@@ -99,6 +103,7 @@ def load():
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
                  "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
                  "fr_batch_create", "fr_batch_step", "fr_batch_set_stream", "fr_batch_destroy",
+                 "fr_set_tiles", "fr_get_tiles", "fr_autotune",
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
                  "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
                  "fr_mlp_get_params", "fr_mlp_get_bf16", "fr_mlp_forward", "fr_mlp_loss_grad",
@@ -123,25 +128,32 @@ VISCOUS = {"br2": 0, "ldg": 1}
 
 
 def _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, ref=(1.0, 0.0), viscous="br2",
-          ldg_tau=0.1):
+          ldg_tau=0.1, bc_tag=None, wall_T=1.0):
     ev = np.ascontiguousarray(mesh.elem_vert, dtype=np.int64)
     nodes = np.ascontiguousarray(mesh.elem_nodes, dtype=np.float64)
     keep.extend([ev, nodes])
+    tags = None
+    if bc_tag is not None:
+        tags = np.ascontiguousarray(bc_tag, dtype=np.int32)
+        assert tags.shape == (ev.shape[0], 6)
+        keep.append(tags)
     return fr_mesh_desc(p=int(p), q=int(mesh.q), n_elem=int(ev.shape[0]), elem_vert=ev.ctypes.data,
                         elem_nodes=nodes.ctypes.data, gamma=gamma, prandtl=prandtl, mu=mu,
                         br2_eta=eta, flux=FLUX[flux], prec=PREC[prec],
                         check_finite=int(bool(check_finite)), viscous=VISCOUS[viscous],
-                        ref_rho=float(ref[0]), ref_p=float(ref[1]), ldg_tau=float(ldg_tau))
+                        ref_rho=float(ref[0]), ref_p=float(ref[1]), ldg_tau=float(ldg_tau),
+                        bc_tag=tags.ctypes.data if tags is not None else None, wall_T=float(wall_T))
 
 
-def geometry_host(mesh, p: int, eta: float = 6.0):
+def geometry_host(mesh, p: int, eta: float = 6.0, bc_tag=None):
     """Host-only mesh setup (fr_mesh_geometry_host): geo, fgeo, ftab, conn, xyz as numpy arrays."""
     keep = []
-    d = _desc(mesh, p, 0.0, 1.4, 0.72, eta, "rusanov", "fp64", False, keep)
+    d = _desc(mesh, p, 0.0, 1.4, 0.72, eta, "rusanov", "fp64", False, keep, bc_tag=bc_tag)
     E, Ns, Nfp = d.n_elem, (p + 1) ** 3, (p + 1) ** 2
+    F = 3 * E + (int(np.sum(np.asarray(bc_tag) == 1)) // 2 if bc_tag is not None else 0)
     geo = np.empty((E, 10, Ns))
-    fgeo = np.empty((3 * E, 4, Nfp))
-    ftab = np.empty((3 * E, 4), dtype=np.int32)
+    fgeo = np.empty((F, 4, Nfp))
+    ftab = np.empty((F, 4), dtype=np.int32)
     conn = np.empty((E, 6, 2), dtype=np.int32)
     xyz = np.empty((E, 3, Ns))
     _check(load().fr_mesh_geometry_host(ctypes.byref(d), geo.ctypes.data, fgeo.ctypes.data,
@@ -163,14 +175,14 @@ class FRMesh:
     def __init__(self, mesh, p: int, *, mu: float = 0.0, gamma: float = 1.4, prandtl: float = 0.72,
                  eta: float = 6.0, flux: str = "rusanov", prec: str = "fp64", check_finite: bool = False,
                  stream=None, ref_rho: float = 1.0, ref_p: float = 0.0, viscous: str = "br2",
-                 ldg_tau: float = 0.1):
+                 ldg_tau: float = 0.1, bc_tag=None, wall_T: float = 1.0):
         L = load()
         self.p = int(p)
         self.Ns = (self.p + 1) ** 3
         self.E = int(mesh.elem_vert.shape[0])
         keep = []
         d = _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, (ref_rho, ref_p), viscous,
-                  ldg_tau)
+                  ldg_tau, bc_tag, wall_T)
         self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
         h = ctypes.c_void_p()
         _check(L.fr_mesh_create(ctypes.byref(d), self._stream, ctypes.byref(h)))
@@ -241,6 +253,20 @@ class FRMesh:
         out = np.zeros(2)
         _check(load().fr_kinetic_energy(self.h, out.ctypes.data))
         return float(out[0]), float(out[1])
+
+    def set_tiles(self, epb: int, fbs: int):
+        _check(load().fr_set_tiles(self.h, int(epb), int(fbs)))
+
+    def tiles(self):
+        e, f = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().fr_get_tiles(self.h, ctypes.byref(e), ctypes.byref(f)))
+        return e.value, f.value
+
+    def autotune(self, n_trials: int = 3):
+        """Time the 6 tile choices (fr_autotune); returns ((epb, fbs) chosen, ms per choice)."""
+        ms = np.zeros(6)
+        _check(load().fr_autotune(self.h, int(n_trials), ms.ctypes.data))
+        return self.tiles(), ms
 
     def set_body_force(self, g):
         """Constant body force per unit mass (3 values; None or zeros switch it off)."""

@@ -1,0 +1,58 @@
+"""The tile autotuner: every tile choice (elements per block of the element kernels, threads per
+block of the face kernel) gives the same residual and RK step bit for bit (each thread does
+the same arithmetic), and the autotuner keeps the fastest choice it timed."""
+import numpy as np
+import pytest
+
+from paper_2308_06605_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _fr():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_06605_amd import fr
+
+    fr.load()
+    return fr
+
+
+@pytest.mark.parametrize("p,viscous", [(2, "br2"), (3, "br2"), (3, "ldg"), (5, "br2")])
+def test_tiles_bitwise_equal(p, viscous):
+    fr = _fr()
+    m = I.box_mesh(5, q=2, curve_amp=0.04)
+    g = fr.FRMesh(m, p, mu=1e-3, flux="roe", viscous=viscous)
+    X = g.sol_coords()
+    U0 = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=1, amp=0.01)
+    g.set_state(U0)
+    assert g.tiles() == (0, 0)
+    R0 = g.residual()
+    g.rk_step(1e-3, "lsrk45", 2)
+    S0 = g.get_state()
+    for epb in (0, 1):
+        for fbs in (0, 1, 2):
+            g.set_tiles(epb, fbs)
+            g.set_state(U0)
+            assert np.array_equal(g.residual(), R0), (epb, fbs)
+            g.rk_step(1e-3, "lsrk45", 2)
+            assert np.array_equal(g.get_state(), S0), (epb, fbs)
+    with pytest.raises(fr.FRError):
+        g.set_tiles(2, 0)
+    g.close()
+
+
+def test_autotune_picks_fastest():
+    fr = _fr()
+    m = I.box_mesh(16, q=1)
+    g = fr.FRMesh(m, 3, mu=1e-3, flux="roe")
+    g.set_state(I.state_from_coords(g.sol_coords(), I.tgv_state))
+    R0 = g.residual()
+    (epb, fbs), ms = g.autotune(3)
+    print("tile timings (ms per stage):", ms, "chosen", (epb, fbs), flush=True)
+    assert np.all(ms > 0)
+    assert ms[3 * epb + fbs] == ms.min()
+    assert np.array_equal(g.residual(), R0)
+    g.close()

@@ -1,0 +1,132 @@
+"""GPU parity of isothermal no-slip walls against the oracle, through the C ABI, with the FP64
+floor rule (per variable e_v = max|X_gpu - X_ld| / max|X_ld| <= max(1e-12, 4 f_v))."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_06605_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MU = 1.0 / 400.0
+TW = 1.0 / (1.4 * 0.01)
+
+
+def _fr():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_06605_amd import fr
+
+    fr.load()
+    return fr
+
+
+def rel(a, b):
+    return np.abs(a - b).max(axis=(0, 2)) / np.maximum(np.abs(b).max(axis=(0, 2)), 1e-300)
+
+
+def channel(n=(4, 5, 3), q=2, curve=0.05):
+    m = I.box_mesh(n, q=q, periodic=(True, False, True), curve_amp=curve, curve_mode="mixed")
+    return m, I.boundary_tags(m)
+
+
+def _oracles(m, p, flux, tags, nu=None):
+    out = {}
+    for prec in ("f64", "ld"):
+        o = oracle.Oracle(m, p, mu=MU, flux=flux, precision=prec, bc_tag=tags, wall_T=TW)
+        if nu is not None:
+            o.set_eddy_viscosity(nu, 0.9)
+        out[prec] = o
+    return out
+
+
+@pytest.mark.parametrize("p,flux", [(3, "roe"), (2, "rusanov"), (4, "rusanov"), (1, "roe")])
+def test_wall_residual(p, flux):
+    fr = _fr()
+    m, tags = channel(q=min(max(p, 1), 2))
+    g = fr.FRMesh(m, p, mu=MU, flux=flux, bc_tag=tags, wall_T=TW)
+    X = g.sol_coords()
+    U = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=p, amp=0.02)
+    g.set_state(U)
+    R = g.residual()
+    g.close()
+    o = _oracles(m, p, flux, tags)
+    Rl = o["ld"].residual(U)
+    e, f = rel(R, Rl), rel(o["f64"].residual(U), Rl)
+    print(f"walls p={p} {flux} err {e} floor {f}", flush=True)
+    assert np.all(e <= np.maximum(1e-12, 4 * f)), (e, f)
+
+
+def test_wall_rk_and_eddy_viscosity():
+    # a gently curved channel: the residual tests' coarse, strongly curved 4 x 5 x 3 mesh has
+    # elements too distorted to step stably at this dt (periodic or not, with or without nu_t)
+    fr = _fr()
+    p = 3
+    m, tags = channel(n=(4, 6, 4), q=2, curve=0.02)
+    nu = np.random.default_rng(2).uniform(0, 0.004, m.n_elem)
+    g = fr.FRMesh(m, p, mu=MU, flux="roe", bc_tag=tags, wall_T=TW)
+    X = g.sol_coords()
+    U0 = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=7, amp=0.02)
+    g.set_state(U0)
+    g.set_eddy_viscosity(nu)
+    g.rk_step(1e-3, "lsrk45", 2)
+    U2 = g.get_state()
+    g.close()
+    o = _oracles(m, p, "roe", tags, nu)
+    Ul, Uo = o["ld"].rk_step(U0, 1e-3, "lsrk45", 2), o["f64"].rk_step(U0, 1e-3, "lsrk45", 2)
+    e, f = rel(U2, Ul), rel(Uo, Ul)
+    print(f"walls rk err {e} floor {f}", flush=True)
+    assert np.all(e <= np.maximum(1e-12, 4 * f)), (e, f)
+
+
+def test_rest_state_steady_and_mass_conserved():
+    fr = _fr()
+    p = 3
+    m, tags = channel()
+    g = fr.FRMesh(m, p, mu=MU, flux="roe", bc_tag=tags, wall_T=TW)
+    X = g.sol_coords()
+    U = np.zeros((m.n_elem, 5, (p + 1) ** 3))
+    U[:, 0] = 1.0
+    U[:, 4] = TW / 0.4
+    g.set_state(U)
+    assert np.abs(g.residual()).max() < 1e-10
+    U = I.state_from_coords(X, I.tgv_state)
+    g.set_state(U)
+    R = g.residual()
+    g.close()
+    _, dJ, _, _ = oracle.Oracle(m, p, bc_tag=tags).geometry()
+    w = np.polynomial.legendre.leggauss(p + 1)[1]
+    W = np.einsum("k,j,i->kji", w, w, w).ravel()
+    tot = np.einsum("es,es,s->", R[:, 0], dJ, W)
+    mag = np.einsum("es,es,s->", np.abs(R[:, 0]), dJ, W)
+    assert abs(tot) / mag < 1e-13
+
+
+def test_wall_errors_and_batch():
+    fr = _fr()
+    m, tags = channel(n=(3, 4, 3), q=1, curve=0.0)
+    with pytest.raises(fr.FRError) as ei:
+        fr.FRMesh(m, 2, mu=MU)
+    assert ei.value.name == "FR_ERR_MESH"
+    with pytest.raises(fr.FRError) as ei:
+        fr.FRMesh(m, 2, mu=MU, bc_tag=tags, prec="fp32", ref_rho=1.0, ref_p=TW)
+    assert ei.value.name == "FR_ERR_UNSUPPORTED"
+    with pytest.raises(fr.FRError) as ei:
+        fr.FRMesh(m, 2, mu=MU, bc_tag=tags, viscous="ldg")
+    assert ei.value.name == "FR_ERR_UNSUPPORTED"
+    # a walled mesh in a batch steps exactly as alone
+    meshes = []
+    for _ in range(2):
+        g = fr.FRMesh(m, 2, mu=MU, flux="roe", bc_tag=tags, wall_T=TW)
+        X = g.sol_coords()
+        g.set_state(I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=1, amp=0.02))
+        meshes.append(g)
+    b = fr.Batch([meshes[0]], [1e-3])
+    b.step(3)
+    meshes[1].rk_step(1e-3, "lsrk45", 3)
+    assert np.array_equal(meshes[0].get_state(), meshes[1].get_state())
+    b.close()
+    for g in meshes:
+        g.close()

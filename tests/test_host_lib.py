@@ -79,3 +79,34 @@ def test_host_setup_errors():
     with pytest.raises(fr.FRError) as ei:
         fr.geometry_host(m, 9)
     assert ei.value.name == "FR_ERR_ARG"
+
+
+def test_host_setup_walls_match_oracle():
+    """A channel (walls in y): wall faces are owned by their element, have no neighbour and the
+    one-sided BR2 factor; every other face as in the periodic case."""
+    p = 3
+    m = I.box_mesh((3, 4, 3), q=2, periodic=(True, False, True), curve_amp=0.05, curve_mode="mixed")
+    tags = I.boundary_tags(m)
+    geo, fgeo, ftab, conn, xyz = fr.geometry_host(m, p, bc_tag=tags)
+    o = oracle.Oracle(m, p, bc_tag=tags)
+    nbr, nface, owner, _ = o.connectivity()
+    _, _, Nf, Jf = o.geometry()
+    E = m.n_elem
+    walls = tags == 1
+    assert np.array_equal(conn[:, :, 0], nbr)
+    assert np.all(conn[walls, 0] == -1) and np.all((conn[walls, 1] >> 6) & 1 == 1)
+    assert np.all((conn[walls, 1] >> 7) & 1 == 1)
+    assert np.array_equal((conn[:, :, 1] >> 6) & 1, owner)
+    owners = [(e, f) for e in range(E) for f in range(6) if owner[e, f]]
+    assert len(owners) == ftab.shape[0] == 3 * E + walls.sum() // 2
+    eta, cl = 6.0, (p + 1) ** 2 / 2
+    for fid, (e, f) in enumerate(owners):
+        assert ftab[fid, 0] == e and (ftab[fid, 2] & 7) == f
+        if walls[e, f]:
+            assert ftab[fid, 1] == -1 and (ftab[fid, 2] >> 9) & 1 == 1
+            assert np.allclose(fgeo[fid, 3], eta * cl * (2 / Jf[e, f]) / 4, rtol=1e-14)
+        else:
+            assert (ftab[fid, 2] >> 9) & 1 == 0
+        assert np.abs(fgeo[fid, :3, :].T - Nf[e, f]).max() < 1e-14 * max(1.0, np.abs(Nf).max())
+    with pytest.raises(fr.FRError):
+        fr.geometry_host(m, p)  # untagged boundary faces are an error
