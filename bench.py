@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--dt", type=float, default=2.5e-4)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"],
                     help="fp32: FP32 operators and fluxes with FP64 state and mass equation")
+    ap.add_argument("--tiles", type=int, nargs=2, default=None, metavar=("EPB", "FBS"),
+                    help="fixed tile shapes (fr_set_tiles) instead of running the autotuner")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip timing the FP32 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -137,6 +139,13 @@ def main():
     U = inputs.state_from_coords(X, inputs.tgv_state)
     g.set_state(U)
     torch.cuda.synchronize()
+    # tile shapes: the autotuner's choice on this mesh (FP64 path), or fixed ones
+    tile_ms = None
+    if args.tiles is not None:
+        g.set_tiles(*args.tiles)
+    elif args.prec == "fp64":
+        _, tile_ms = g.autotune(2)
+    tiles = g.tiles()
 
     stages = STAGES[args.scheme]
     for _ in range(args.warmup):
@@ -231,6 +240,9 @@ def main():
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl, "n_elem": mesh.n_elem, "dof": dof, "p": args.p,
+                   "tiles": {"elements_per_block": ("256/Ns", "half of 256/Ns")[tiles[0]],
+                             "face_block": (256, 128, 64)[tiles[1]],
+                             "autotune_ms_per_stage": None if tile_ms is None else [float(x) for x in tile_ms]},
                    "stages_per_step": stages, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
