@@ -87,8 +87,8 @@ enum fr_scheme {                                  /* explicit Runge-Kutta scheme
  *              no-slip wall at temperature wall_T (p/rho, > 0). Its inviscid flux is the Riemann
  *              flux against the mirror state (rho, -m, E) (impermeable, no energy flux); its
  *              viscous flux uses the wall state (rho, 0, rho wall_T/(gamma-1)) as the common
- *              state and the one-sided BR2 gradient. Walls need prec = FR_FP64 and FR_BR2
- *              (FR_ERR_UNSUPPORTED otherwise).
+ *              state and the one-sided BR2 gradient. Walls need FR_BR2 (FR_ERR_UNSUPPORTED with
+ *              FR_LDG); both precisions support them.
  *   flux       enum fr_flux.   prec: enum fr_prec.
  *   check_finite  non-zero: fr_residual scans its result and reports FR_ERR_NONFINITE.
  *   ref_rho, ref_p  reference state at rest used by FR_FP32 (ignored by FR_FP64): the FP32
@@ -138,19 +138,19 @@ int fr_sol_coords(fr_mesh_t m, double *xyz);
 int fr_set_state(fr_mesh_t m, const double *U, int on_device);
 int fr_get_state(fr_mesh_t m, double *U, int on_device);
 
-/* Tile shapes of the FP64 stage kernels, chosen by the autotuner or by the caller:
+/* Tile shapes of the stage kernels (both precisions), chosen by the autotuner or by the caller:
  *   epb  elements per block of the element kernels (pre-pass, volume): 0 = 256/N_s (at least
  *        one), 1 = half of that (at least one);
  *   fbs  threads per block of the face kernel: 0 = 256, 1 = 128, 2 = 64.
- * Results are bitwise independent of the tiles (every thread does the same arithmetic). The
- * FP32 form keeps its default tiles. A batch captures the tiles in force at its creation. */
+ * Results are bitwise independent of the tiles (every thread does the same arithmetic). A batch
+ * captures the tiles in force at its creation. */
 int fr_set_tiles(fr_mesh_t m, int32_t epb, int32_t fbs);
 int fr_get_tiles(fr_mesh_t m, int32_t *epb, int32_t *fbs);
 
 /* Autotuner: time each of the 6 tile choices on this mesh and state with n_trials residual
  * stages (HIP events on the handle's stream, after one warm-up stage each) and keep the fastest.
  * ms (may be NULL) receives the mean ms per stage of (epb, fbs) = (0,0), (0,1), (0,2), (1,0),
- * (1,1), (1,2). Allocates a scratch residual for the call; waits. The FP32 form returns zeros. */
+ * (1,1), (1,2). Allocates a scratch residual for the call; waits. */
 int fr_autotune(fr_mesh_t m, int n_trials, double *ms);
 
 /* Source term S of Eq. (3) as a constant body force per unit mass g[3] ("body forcing" is

@@ -1,13 +1,15 @@
 """Many uneven meshes advanced together: the batched workload and its throughput measurement.
 
-Workload (seeded with numpy.random.default_rng(seed)): n_mesh periodic box meshes on
-[0, 2 pi)^3, element counts drawn log-uniformly from [8^3, 40^3] (n = round(cbrt(N)) elements
-per direction), degree p uniform in {2, 3, 4, 5}, a uniform flow at Mach 0.2 to 0.5 (|u| = 1)
-with a seeded smooth random perturbation, Roe + BR2 at mu = 1e-4, the FP32 form (FP32 operators
-and fluxes, FP64 state and mass equation) and LSRK45 with dt from the stability estimate
-dt = 1.5 h / ((|u| + c)(p + 1)(p + 2) 1.7). By default the meshes are fully periodic; with
---walls they are channels, periodic in x and z with isothermal no-slip walls in y at the flow's
-temperature (the flow then runs along x), in FP64 (walls need the FP64 path).
+Workload (seeded with numpy.random.default_rng(seed)): n_mesh channel meshes on [0, 2 pi)^3,
+periodic in x and z with isothermal no-slip walls in y at the flow's temperature, element counts
+drawn log-uniformly from [8^3, 40^3] (n = round(cbrt(N)) elements per direction), degree p
+uniform in {2, 3, 4, 5}, a uniform flow along x at Mach 0.2 to 0.5 (|u| = 1) with a seeded
+smooth random perturbation, Roe + BR2 at mu = 1e-4, the FP32 form (FP32 operators and fluxes,
+FP64 state and mass equation) and LSRK45 with dt from the stability estimate
+dt = 1.5 h / ((|u| + c)(p + 1)(p + 2) 1.7). Each mesh's tile shapes come from the autotuner
+(fr_autotune) before anything is timed. --periodic makes fully periodic boxes instead (the flow
+direction is then (1, 0.5, 0.25) normalised), --fp64 runs the FP64 kernels, --no-autotune keeps the
+default tiles.
 
 Two ways to run the same steps are timed on the same meshes and state:
   sequential  fr_rk_step on each mesh in turn (15 kernel launches per mesh and step),
@@ -47,16 +49,17 @@ def stable_dt(n: int, p: int, mach: float) -> float:
     return 1.5 * h / ((1.0 + c) * (p + 1) * (p + 2) * 1.7)
 
 
-def build(fr, spec, walls=False):
+def build(fr, spec, walls=True, prec="fp32"):
     p0 = 1.0 / (GAMMA * spec["mach"] ** 2)
+    kw = dict(prec="fp32", ref_rho=1.0, ref_p=p0) if prec == "fp32" else {}
     if walls:
         m = I.box_mesh(spec["n"], q=1, periodic=(True, False, True))
-        g = fr.FRMesh(m, spec["p"], mu=MU, flux="roe", bc_tag=I.boundary_tags(m), wall_T=p0)
+        g = fr.FRMesh(m, spec["p"], mu=MU, flux="roe", bc_tag=I.boundary_tags(m), wall_T=p0, **kw)
         X = g.sol_coords()
         U = I.state_from_coords(X, I.freestream_state, mach=spec["mach"], direction=(1.0, 0.0, 0.0))
     else:
         m = I.box_mesh(spec["n"], q=1)
-        g = fr.FRMesh(m, spec["p"], mu=MU, flux="roe", prec="fp32", ref_rho=1.0, ref_p=p0)
+        g = fr.FRMesh(m, spec["p"], mu=MU, flux="roe", **kw)
         X = g.sol_coords()
         U = I.state_from_coords(X, I.freestream_state, mach=spec["mach"])
     U += I.random_smooth_perturbation(X, seed=spec["seed"], amp=0.01)
@@ -64,7 +67,7 @@ def build(fr, spec, walls=False):
     return g, U
 
 
-def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=False):
+def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune=True):
     import torch
 
     from . import fr
@@ -74,11 +77,14 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=False):
     t0 = time.time()
     meshes, states, dts = [], [], []
     for s in specs:
-        g, U = build(fr, s, walls)
+        g, U = build(fr, s, walls, prec)
         meshes.append(g)
         states.append(U)
         dts.append(stable_dt(s["n"], s["p"], s["mach"]))
     setup_s = time.time() - t0
+    t0 = time.time()
+    tiles = [g.autotune(3)[0] if autotune else g.tiles() for g in meshes]
+    autotune_s = time.time() - t0
     dof = sum(g.E * g.Ns for g in meshes)
     stages = 5
     stream = torch.cuda.current_stream()
@@ -118,18 +124,20 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=False):
     b.close()
     for g in meshes:
         g.close()
+    geo = "channel meshes (isothermal walls in y)" if walls else "periodic box meshes"
     out = {
-        "workload": f"{n_mesh} {'channel meshes (isothermal walls in y)' if walls else 'periodic box meshes'}, "
-                    f"log-uniform 8^3..40^3 elements, p in 2..5, Mach 0.2-0.5, Roe+BR2 mu={MU}, "
-                    f"{'FP64' if walls else 'FP32 form'}, LSRK45, seed {seed}",
+        "workload": f"{n_mesh} {geo}, log-uniform 8^3..40^3 elements, p in 2..5, Mach 0.2-0.5, "
+                    f"Roe+BR2 mu={MU}, {'FP32 form' if prec == 'fp32' else 'FP64'}, LSRK45, "
+                    f"{'autotuned' if autotune else 'default'} tiles, seed {seed}",
         "n_mesh": n_mesh, "dof": int(dof), "elements": int(sum(g.E for g in meshes)),
         "steps": steps, "stages_per_step": stages,
         "sequential": {"ms_per_step": ms_seq, "dof_updates_per_s": dof * stages / (ms_seq * 1e-3)},
         "batch_graph": {"ms_per_step": ms_batch, "dof_updates_per_s": dof * stages / (ms_batch * 1e-3),
                         "capture_s": capture_s},
         "speedup": ms_seq / ms_batch, "bitwise_equal": bool(same), "finite": bool(finite),
-        "setup_s": setup_s,
-        "meshes": [dict(s, dt=dt) for s, dt in zip(specs, dts)],
+        "setup_s": setup_s, "autotune_s": autotune_s,
+        "tiles_chosen": {f"{e},{f}": sum(1 for t in tiles if tuple(t) == (e, f)) for e in (0, 1) for f in (0, 1, 2)},
+        "meshes": [dict(s, dt=dt, tiles=list(t)) for s, dt, t in zip(specs, dts, tiles)],
     }
     return out
 
@@ -140,10 +148,13 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--walls", action="store_true")
+    ap.add_argument("--periodic", action="store_true", help="fully periodic boxes instead of channels")
+    ap.add_argument("--fp64", action="store_true", help="the FP64 kernels instead of the FP32 form")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = run(a.n_mesh, a.steps, a.warmup, a.seed, a.walls)
+    res = run(a.n_mesh, a.steps, a.warmup, a.seed, not a.periodic, "fp64" if a.fp64 else "fp32",
+              not a.no_autotune)
     line = {k: v for k, v in res.items() if k != "meshes"}
     print(json.dumps(line), flush=True)
     if a.out:

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 // (s F^{I,perp} - F^d_f) g'(xi_d), R = -div/|J|, and the RK register update.
 // ------------------------------------------------------------------------------------------
 template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX>
-__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P)) void k_volume(
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS)) void k_volume(
     const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
     double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2,
@@ -334,12 +334,6 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P)) vo
   __syncthreads();
   real F[3][5];
   if (act) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const real ei[3] = {real(i == 0), real(i == 1), real(i == 2)};
-      real un_, c_;
-      flux_n(U, ei, ph, F[i], un_, c_);
-    }
     if (VISC) {
       real dU[3][5];
 #pragma unroll
@@ -374,18 +368,22 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P)) vo
           g += ja[6 + i] * dU[2][v];
           G[i][v] = iJ * g;
         }
-      real Fv[3][5];
       real mu = ph.mu, kap = ph.kappa;
       if (SGS) {
         const real mut = U[0] * real(nut[e]);
         mu += mut;
         kap += mut * kt;
       }
-      visc_flux_mk(U, G, ph.gm1, mu, kap, Fv);
+      visc_flux_mk(U, G, ph.gm1, mu, kap, F);
+    }
+    // the inviscid flux after the viscous one: F is not live across the gradient phase
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i) {
+      const real ei[3] = {real(i == 0), real(i == 1), real(i == 2)};
+      real Fi[5], un_, c_;
+      flux_n(U, ei, ph, Fi, un_, c_);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) F[i][v] -= Fv[i][v];
+      for (int v = 0; v < 5; ++v) F[i][v] = VISC ? Fi[v] - F[i][v] : Fi[v];
     }
   }
   // transformed flux F^d = sum_i Ja[d][i] F_i for the three directions; the metric terms are
@@ -1026,7 +1024,6 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->bc_tag, d->br2_eta, H);
   if (!err.empty()) return fail(FR_ERR_MESH, err);
   if (H.n_wall > 0) {
-    if (d->prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "walls need prec = FR_FP64");
     if (d->viscous == FR_LDG) return fail(FR_ERR_UNSUPPORTED, "walls need the BR2 viscous flux");
     if (!(d->wall_T > 0.0) || !std::isfinite(d->wall_T)) return fail(FR_ERR_ARG, "wall_T must be finite and > 0");
   }
@@ -1302,11 +1299,6 @@ int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
   if (n_trials < 1) return fail(FR_ERR_ARG, "n_trials must be >= 1");
   DeviceMesh &dm = m->dm;
-  if (dm.prec != FR_FP64) {  // the FP32 form keeps its default tiles
-    if (ms)
-      for (int i = 0; i < 6; ++i) ms[i] = 0.0;
-    return FR_OK;
-  }
   const int64_t M = dm.E * 5 * dm.Ns;
   double *tmp = nullptr;
   HIPCHK(hipMalloc(&tmp, M * sizeof(double)));

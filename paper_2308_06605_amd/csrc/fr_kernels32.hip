@@ -124,14 +124,14 @@ __device__ __forceinline__ void full_state(const float Up[5], const Ref32 &r, fl
 // ------------------------------------------------------------------------------------------
 // K1 (FP32 form): U' and its broken gradient to the faces in FP32, momentum to the faces in FP64
 // ------------------------------------------------------------------------------------------
-template <int P, bool VISC>
-__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass32(const double *__restrict__ X,
-                                                             const float *__restrict__ geo32,
-                                                             float *__restrict__ face32,
-                                                             double *__restrict__ facem, int64_t E,
-                                                             OpsT<float> ops, OpsT<double> opsd, Ref32 ref) {
+template <int P, bool VISC, int EPBX>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *__restrict__ X,
+                                                                 const float *__restrict__ geo32,
+                                                                 float *__restrict__ face32,
+                                                                 double *__restrict__ facem, int64_t E,
+                                                                 OpsT<float> ops, OpsT<double> opsd, Ref32 ref) {
   using C = Cfg<P>;
-  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int NG = VISC ? 15 : 1;
   __shared__ float sU[EPB][5][NS];
   __shared__ double sM[EPB][3][NS];
@@ -210,18 +210,76 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_prepass32(const double *__res
 //   fout32 [F][9][Nfp]: J' = (U'_R - U'_L)/2 (5), owner's momentum flux (3), reduced energy (1)
 //   foutm  [F][Nfp]   : owner's mass flux (FP64)
 // ------------------------------------------------------------------------------------------
-template <int P, bool VISC>
-__global__ __launch_bounds__(256) void k_face32(const float *__restrict__ face32, const double *__restrict__ facem,
+// Isothermal no-slip wall (face record with kFaceWall, owner side only) in the reduced
+// variables. Inviscid part: the Riemann flux against the mirror state (rho', -m, E'), whose mass
+// and reduced energy fluxes vanish (the central mass flux (m - m)/2 . N is exactly zero).
+// Viscous part: the wall state U_w = (rho_L, 0, rho_L T_w/(gamma-1)) as the common state with the
+// one-sided BR2 gradient G_L + 2 sigma N (U_w - U_L). The energy jump is formed as
+// E'_w - E'_L = c_w + rho'_L T_w/(gamma-1) - E'_L, with c_w = rho_r T_w/(gamma-1) - E_r taken in
+// FP64 on the host, so no FP32 difference of two reference-sized energies is taken.
+template <bool VISC>
+__device__ __forceinline__ void wall_face32(const float *srcL, const double *fg, int NFP, const Phys<float> &ph,
+                                            const Ref32 &ref, int flux, float tw_gm1, float cw, float *dst,
+                                            double *dmass) {
+  float UL[5], UG[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) UL[v] = srcL[v * NFP];
+  UG[0] = UL[0];
+  UG[1] = -UL[1];
+  UG[2] = -UL[2];
+  UG[3] = -UL[3];
+  UG[4] = UL[4];
+  const float NL[3] = {float(fg[0]), float(fg[NFP]), float(fg[2 * NFP])};
+  const float nm = sqrtf(NL[0] * NL[0] + NL[1] * NL[1] + NL[2] * NL[2]);
+  const float inm = 1.0f / nm;
+  const float nh[3] = {NL[0] * inm, NL[1] * inm, NL[2] * inm};
+  float Fr[5];
+  riemann32(UL, UG, nh, ph, ref, flux, Fr);
+  float Jw[5] = {0, 0, 0, 0, 0};
+  if (VISC) {
+    Jw[1] = -UL[1];
+    Jw[2] = -UL[2];
+    Jw[3] = -UL[3];
+    Jw[4] = cw + UL[0] * tw_gm1 - UL[4];
+    const float sig2 = 2.0f * float(fg[3 * NFP]);
+    float GI[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) GI[i][v] = srcL[(5 + i * 5 + v) * NFP] + sig2 * NL[i] * Jw[v];
+    float UW[5];
+    UW[0] = ref.rho + UL[0];
+    UW[1] = UW[2] = UW[3] = 0.0f;
+    UW[4] = UW[0] * tw_gm1;
+    float Fv[3][5];
+    visc_flux(UW, GI, ph, Fv);
+#pragma unroll
+    for (int v = 1; v < 5; ++v) Fr[v] -= Fv[0][v] * nh[0] + Fv[1][v] * nh[1] + Fv[2][v] * nh[2];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(Jw[v], &dst[v * NFP]);
+#pragma unroll
+  for (int v = 1; v < 5; ++v) __builtin_nontemporal_store(nm * Fr[v], &dst[(4 + v) * NFP]);
+  __builtin_nontemporal_store(double(nm * Fr[0]), dmass);
+}
+
+template <int P, bool VISC, int FBS>
+__global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32, const double *__restrict__ facem,
                                                 const double *__restrict__ fgeo, const FaceRec *__restrict__ ftab,
-                                                int64_t F, Phys<float> ph, Ref32 ref, int flux,
-                                                float *__restrict__ fout32, double *__restrict__ foutm) {
+                                                int64_t F, Phys<float> ph, Ref32 ref, int flux, float tw_gm1,
+                                                float cw, float *__restrict__ fout32, double *__restrict__ foutm) {
   constexpr int N = P + 1, NFP = N * N;
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * FBS + threadIdx.x;
   const int64_t fc = gid / NFP;
   if (fc >= F) return;
   const int kk = (int)(gid - fc * NFP);
   const FaceRec r = ftab[fc];
   const int fL = r.code & 7, fR = (r.code >> 3) & 7;
+  if (r.code & kFaceWall) {
+    wall_face32<VISC>(face32 + (((int64_t)r.eL * 6 + fL) * 20) * NFP + kk, fgeo + (fc * 4) * NFP + kk, NFP, ph, ref,
+                      flux, tw_gm1, cw, fout32 + (fc * 9) * NFP + kk, foutm + fc * NFP + kk);
+    return;
+  }
   const bool swp = (r.code >> 6) & 1, flu = (r.code >> 7) & 1, flv = (r.code >> 8) & 1;
   const int a = kk % N, b = kk / N;
   const int uu = swp ? b : a, vv = swp ? a : b;
@@ -275,14 +333,14 @@ __global__ __launch_bounds__(256) void k_face32(const float *__restrict__ face32
 // K3 (FP32 form): corrected gradient, reduced fluxes, divergence + correction in FP32 for
 // momentum and reduced energy, in FP64 for mass; R_E = R''_E + H_r R_rho; RK update in FP64.
 // ------------------------------------------------------------------------------------------
-template <int P, bool VISC>
-__global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
+template <int P, bool VISC, int EPBX>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) void k_volume32(
     const double *__restrict__ X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
     const float *__restrict__ fout32, const double *__restrict__ foutm, int64_t E, OpsT<float> ops,
     OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *__restrict__ out0,
     double *__restrict__ reg1, double *__restrict__ reg2) {
   using C = Cfg<P>;
-  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = C::EPB;
+  constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int R = (NF + NS - 1) / NS;
   constexpr int NJ = (VISC ? 9 : 4) * NF;  // [4][NF] flux (mom 3, reduced energy), [5][NF] jumps
   __shared__ float sUall[EPB][5 * NS];     // U', later 4 components of the transformed flux
@@ -341,12 +399,6 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
     float Up[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) Up[v] = sU[v * NS + t];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const float ei[3] = {float(i == 0), float(i == 1), float(i == 2)};
-      float un_, c_, pp_, hp_;
-      reduced_flux_n(Up, ei, ph, ref, F[i], un_, c_, pp_, hp_);
-    }
     if (VISC) {
       float ja[9];
 #pragma unroll
@@ -382,12 +434,16 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
         for (int v = 0; v < 5; ++v) G[i][v] = iJ * (ja[i] * dU[0][v] + ja[3 + i] * dU[1][v] + ja[6 + i] * dU[2][v]);
       float Uf[5];
       full_state(Up, ref, Uf);
-      float Fv[3][5];
-      visc_flux(Uf, G, ph, Fv);
+      visc_flux(Uf, G, ph, F);
+    }
+    // the inviscid flux after the viscous one: F is not live across the gradient phase
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i) {
+      const float ei[3] = {float(i == 0), float(i == 1), float(i == 2)};
+      float Fi[5], un_, c_, pp_, hp_;
+      reduced_flux_n(Up, ei, ph, ref, Fi, un_, c_, pp_, hp_);
 #pragma unroll
-        for (int v = 1; v < 5; ++v) F[i][v] -= Fv[i][v];
+      for (int v = 1; v < 5; ++v) F[i][v] = VISC ? Fi[v] - F[i][v] : Fi[v];
     }
     // transformed fluxes per direction
 #pragma unroll
@@ -498,7 +554,7 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_volume32(
     }                                                            \
   } while (0)
 
-template <int P, bool VISC>
+template <int P, bool VISC, int EPBX, int FBS>
 int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
                double *ms, std::string &err) {
   using C = Cfg<P>;
@@ -527,24 +583,28 @@ int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, doub
   ref.E = float(ref.E_d);
   ref.H = float(ref.H_d);
   ref.p = float(dm.ref_p);
-  const int64_t blocks = (dm.E + C::EPB - 1) / C::EPB;
-  const int64_t fblocks = (dm.F * C::NFP + 255) / 256;
+  const double tw_gm1 = dm.wall_T / (dm.phys.gamma - 1.0);
+  const float cw = float(ref.rho_d * tw_gm1 - ref.E_d);
+  const int64_t blocks = (dm.E + EPBX - 1) / EPBX;
+  const int64_t fblocks = (dm.F * C::NFP + FBS - 1) / FBS;
   hipStream_t s = (hipStream_t)dm.stream;
   hipEvent_t ev[4];
   if (ms) {
     for (int i = 0; i < 4; ++i) HIPCHK32(hipEventCreate(&ev[i]));
     HIPCHK32(hipEventRecord(ev[0], s));
   }
-  hipLaunchKernelGGL((k_prepass32<P, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X, (const float *)dm.geo32,
+  hipLaunchKernelGGL((k_prepass32<P, VISC, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
+                     (const float *)dm.geo32,
                      (float *)dm.face32, (double *)dm.facem, dm.E, ops, opsd, ref);
   HIPCHK32(hipGetLastError());
   if (ms) HIPCHK32(hipEventRecord(ev[1], s));
-  hipLaunchKernelGGL((k_face32<P, VISC>), dim3((unsigned)fblocks), dim3(256), 0, s, (const float *)dm.face32,
+  hipLaunchKernelGGL((k_face32<P, VISC, FBS>), dim3((unsigned)fblocks), dim3(FBS), 0, s, (const float *)dm.face32,
                      (const double *)dm.facem, (const double *)dm.fgeo, dm.ftab, dm.F, ph, ref, dm.flux,
-                     (float *)dm.fout32, (double *)dm.foutm);
+                     float(tw_gm1), cw, (float *)dm.fout32, (double *)dm.foutm);
   HIPCHK32(hipGetLastError());
   if (ms) HIPCHK32(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL((k_volume32<P, VISC>), dim3((unsigned)blocks), dim3(C::BLOCK), 0, s, X, (const double *)dm.geo,
+  hipLaunchKernelGGL((k_volume32<P, VISC, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
+                     (const double *)dm.geo,
                      dm.fref, (const float *)dm.fout32, (const double *)dm.foutm, dm.E, ops, opsd, ph, ref, st, out0,
                      reg1, reg2);
   HIPCHK32(hipGetLastError());
@@ -561,18 +621,34 @@ int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, doub
   return 0;
 }
 
+// The tile shapes, as for the FP64 kernels: elements per block 256/N_s or half of it
+// (DeviceMesh::tile_epb 0 / 1) and a face block of 256, 128 or 64 threads (tile_fbs 0 / 1 / 2).
+template <int P, bool VISC>
+int launch32_tiles(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
+                   std::string &err) {
+  constexpr int E0 = Cfg<P>::EPB, E1 = E0 > 1 ? E0 / 2 : 1;
+  if (dm.tile_epb == 0) {
+    if (dm.tile_fbs == 0) return launch32_t<P, VISC, E0, 256>(dm, X, st, o, r1, r2, ms, err);
+    if (dm.tile_fbs == 1) return launch32_t<P, VISC, E0, 128>(dm, X, st, o, r1, r2, ms, err);
+    return launch32_t<P, VISC, E0, 64>(dm, X, st, o, r1, r2, ms, err);
+  }
+  if (dm.tile_fbs == 0) return launch32_t<P, VISC, E1, 256>(dm, X, st, o, r1, r2, ms, err);
+  if (dm.tile_fbs == 1) return launch32_t<P, VISC, E1, 128>(dm, X, st, o, r1, r2, ms, err);
+  return launch32_t<P, VISC, E1, 64>(dm, X, st, o, r1, r2, ms, err);
+}
+
 template <bool VISC>
 int launch32_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
                std::string &err) {
   switch (dm.p) {
-    case 0: return launch32_t<0, VISC>(dm, X, st, o, r1, r2, ms, err);
-    case 1: return launch32_t<1, VISC>(dm, X, st, o, r1, r2, ms, err);
-    case 2: return launch32_t<2, VISC>(dm, X, st, o, r1, r2, ms, err);
-    case 3: return launch32_t<3, VISC>(dm, X, st, o, r1, r2, ms, err);
-    case 4: return launch32_t<4, VISC>(dm, X, st, o, r1, r2, ms, err);
-    case 5: return launch32_t<5, VISC>(dm, X, st, o, r1, r2, ms, err);
-    case 6: return launch32_t<6, VISC>(dm, X, st, o, r1, r2, ms, err);
-    case 7: return launch32_t<7, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 0: return launch32_tiles<0, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 1: return launch32_tiles<1, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 2: return launch32_tiles<2, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 3: return launch32_tiles<3, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 4: return launch32_tiles<4, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 5: return launch32_tiles<5, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 6: return launch32_tiles<6, VISC>(dm, X, st, o, r1, r2, ms, err);
+    case 7: return launch32_tiles<7, VISC>(dm, X, st, o, r1, r2, ms, err);
     default: err = "p out of range"; return -5;
   }
 }

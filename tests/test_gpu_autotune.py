@@ -20,11 +20,14 @@ def _fr():
     return fr
 
 
-@pytest.mark.parametrize("p,viscous", [(2, "br2"), (3, "br2"), (3, "ldg"), (5, "br2")])
-def test_tiles_bitwise_equal(p, viscous):
+@pytest.mark.parametrize("p,viscous,prec", [(2, "br2", "fp64"), (3, "br2", "fp64"), (3, "ldg", "fp64"),
+                                            (5, "br2", "fp64"), (2, "br2", "fp32"), (3, "br2", "fp32"),
+                                            (7, "br2", "fp32")])
+def test_tiles_bitwise_equal(p, viscous, prec):
     fr = _fr()
     m = I.box_mesh(5, q=2, curve_amp=0.04)
-    g = fr.FRMesh(m, p, mu=1e-3, flux="roe", viscous=viscous)
+    kw = dict(prec="fp32", ref_rho=1.0, ref_p=1.0 / (1.4 * 0.01)) if prec == "fp32" else {}
+    g = fr.FRMesh(m, p, mu=1e-3, flux="roe", viscous=viscous, **kw)
     X = g.sol_coords()
     U0 = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=1, amp=0.01)
     g.set_state(U0)
@@ -44,14 +47,16 @@ def test_tiles_bitwise_equal(p, viscous):
     g.close()
 
 
-def test_autotune_picks_fastest():
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_picks_fastest(prec):
     fr = _fr()
     m = I.box_mesh(16, q=1)
-    g = fr.FRMesh(m, 3, mu=1e-3, flux="roe")
+    kw = dict(prec="fp32", ref_rho=1.0, ref_p=1.0 / (1.4 * 0.01)) if prec == "fp32" else {}
+    g = fr.FRMesh(m, 3, mu=1e-3, flux="roe", **kw)
     g.set_state(I.state_from_coords(g.sol_coords(), I.tgv_state))
     R0 = g.residual()
     (epb, fbs), ms = g.autotune(3)
-    print("tile timings (ms per stage):", ms, "chosen", (epb, fbs), flush=True)
+    print(prec, "tile timings (ms per stage):", ms, "chosen", (epb, fbs), flush=True)
     assert np.all(ms > 0)
     assert ms[3 * epb + fbs] == ms.min()
     assert np.array_equal(g.residual(), R0)
