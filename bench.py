@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 STAGES = {"lsrk45": 5, "rk4": 4}
+KERNEL_NAMES = {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume", "volume_pre": "k_volume_pre"}
 
 
 def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
@@ -37,8 +38,12 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
                write the jump and common flux (10); per element that is 3 Nfp points
     volume   : read U (5 Ns), volume geometry (10 Ns), its faces' jumps and fluxes (10 Nf) and
                dU (5 Ns); write dU (5 Ns) and U (5 Ns)
-    The stage minimum of any two-pass design (face data written once and read once) is
-    8 (45 Ns + 44 Nf) in FP64; `stage_min` returns it for the roofline of the whole stage.
+    volume_pre (FP64): the volume kernel that also runs the next stage's pre-pass on the state
+               it stores: the volume kernel's bytes plus the pre-pass's writes (20 Nf); its
+               reads of U and the geometry are the volume kernel's own
+    In the FP64 path a stage is face + volume_pre, 8 (25 Ns + 57 Nf) per element. The stage
+    minimum of a two-pass design that reads its inputs in both passes is 8 (45 Ns + 44 Nf);
+    `stage_min` returns that figure for the roofline of the whole stage.
     """
     n = p + 1
     Ns, Nfp = n ** 3, n * n
@@ -55,7 +60,10 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
         k2 = 3 * Nfp * (2 * (4 * nv + 8 * 3) + 8 * 4 + 4 * 9 + 8)
         k3 = 8 * 15 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
     stage_min = 8 * (45 * Ns + 44 * Nf)
-    return {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
+    out = {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
+    if prec == "fp64":
+        out["volume_pre"] = k3 + 8 * nv * Nf
+    return out
 
 
 def make_workload(n: int, p: int, curved: bool):
@@ -113,6 +121,8 @@ def main():
                     help="fp32: FP32 operators and fluxes with FP64 state and mass equation")
     ap.add_argument("--tiles", type=int, nargs=2, default=None, metavar=("EPB", "FBS"),
                     help="fixed tile shapes (fr_set_tiles) instead of running the autotuner")
+    ap.add_argument("--fuse", type=int, choices=(0, 1), default=None,
+                    help="with --tiles: the fused pre-pass on (1, the default) or off (fr_set_fusion)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip timing the FP32 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -139,13 +149,16 @@ def main():
     U = inputs.state_from_coords(X, inputs.tgv_state)
     g.set_state(U)
     torch.cuda.synchronize()
-    # tile shapes: the autotuner's choice on this mesh (FP64 path), or fixed ones
+    # tile shapes and the fused pre-pass: the autotuner's choice on this mesh, or fixed ones
     tile_ms = None
     if args.tiles is not None:
         g.set_tiles(*args.tiles)
-    elif args.prec == "fp64":
+        if args.fuse is not None:
+            g.set_fusion(bool(args.fuse))
+    else:
         _, tile_ms = g.autotune(2)
     tiles = g.tiles()
+    fused = g.fusion()
 
     stages = STAGES[args.scheme]
     for _ in range(args.warmup):
@@ -166,10 +179,12 @@ def main():
     value = dof * stages / (ms_step * 1e-3)
 
     # per-kernel mean launch durations (HIP events on the launch stream)
-    kms = dict(zip(("prepass", "face", "volume"), g.profile_stages(args.dt, args.scheme, 2)))
+    # (FP64: the pre-pass runs once per run of stages, every other stage is face + volume_pre)
+    kms = {k: v for k, v in g.profile_stages(args.dt, args.scheme, 2).items() if v > 0}
     ab = algorithmic_bytes(args.p, args.prec)
     gbs = {k: ab[k] * mesh.n_elem / (kms[k] * 1e-3) / 1e9 for k in kms}
-    dominant = max(kms, key=kms.get)
+    per_stage = ("face", "volume_pre") if "volume_pre" in kms else ("prepass", "face", "volume")
+    dominant = max(per_stage, key=kms.get)
     achieved = gbs[dominant]
     stage_ms = ms_step / stages
     stage_bytes = ab["stage_min"] * mesh.n_elem
@@ -185,7 +200,7 @@ def main():
 
         with open(tfile) as f:
             ts = json.load(f)
-        kname = {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume"}[dominant]
+        kname = KERNEL_NAMES[dominant]
         if args.prec == "fp32":
             kname += "32"
         rec = ts["kernels"].get(kname)
@@ -198,6 +213,10 @@ def main():
         g.close()
         g32 = fr.FRMesh(mesh, args.p, mu=mu, flux=args.flux, prec="fp32", ref_rho=1.0, ref_p=p0)
         g32.set_state(U)
+        if args.tiles is None:
+            g32.autotune(2)
+        else:
+            g32.set_tiles(*args.tiles)
         for _ in range(args.warmup):
             g32.rk_step(args.dt, args.scheme, 1)
         torch.cuda.synchronize()
@@ -206,7 +225,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms32 = e0.elapsed_time(e1) / args.steps
-        k32 = dict(zip(("prepass", "face", "volume"), g32.profile_stages(args.dt, args.scheme, 2)))
+        k32 = {k: v for k, v in g32.profile_stages(args.dt, args.scheme, 2).items() if v > 0}
         ab32 = algorithmic_bytes(args.p, "fp32")
         variants["fp32"] = {
             "value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32, "speedup_vs_fp64": ms_step / ms32,
@@ -242,12 +261,12 @@ def main():
         "config": {"workload": wl, "n_elem": mesh.n_elem, "dof": dof, "p": args.p,
                    "tiles": {"elements_per_block": ("256/Ns", "half of 256/Ns")[tiles[0]],
                              "face_block": (256, 128, 64)[tiles[1]],
+                             "fused_prepass": fused,
                              "autotune_ms_per_stage": None if tile_ms is None else [float(x) for x in tile_ms]},
                    "stages_per_step": stages, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": {"prepass": "k_prepass", "face": "k_face",
-                                "volume": "k_volume"}[dominant] + ("32" if args.prec == "fp32" else ""),
+                     "kernel": KERNEL_NAMES[dominant] + ("32" if args.prec == "fp32" else ""),
                      "bytes_per_launch": ab[dominant] * mesh.n_elem,
                      "mean_launch_ms": kms[dominant]},
         "stage": {"kernel_ms": kms, "kernel_gbs": gbs, "stage_ms": stage_ms,

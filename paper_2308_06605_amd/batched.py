@@ -84,6 +84,7 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune
     setup_s = time.time() - t0
     t0 = time.time()
     tiles = [g.autotune(3)[0] if autotune else g.tiles() for g in meshes]
+    fused = [g.fusion() for g in meshes]
     autotune_s = time.time() - t0
     dof = sum(g.E * g.Ns for g in meshes)
     stages = 5
@@ -137,7 +138,8 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune
         "speedup": ms_seq / ms_batch, "bitwise_equal": bool(same), "finite": bool(finite),
         "setup_s": setup_s, "autotune_s": autotune_s,
         "tiles_chosen": {f"{e},{f}": sum(1 for t in tiles if tuple(t) == (e, f)) for e in (0, 1) for f in (0, 1, 2)},
-        "meshes": [dict(s, dt=dt, tiles=list(t)) for s, dt, t in zip(specs, dts, tiles)],
+        "fused_prepass": sum(fused),
+        "meshes": [dict(s, dt=dt, tiles=list(t), fused=fz) for s, dt, t, fz in zip(specs, dts, tiles, fused)],
     }
     return out
 

@@ -154,37 +154,49 @@ __device__ __forceinline__ double body_force(const StageArgs &st, const double X
 //   SSP(10,4) (out0 = q1 = U, reg1 = q2): stages 0-3 and 5-8 take a forward-Euler step
 //             q1 <- q1 + dt/6 R (stage 0 also sets q2 <- q1); stage 4 then combines
 //             q2 <- q2/25 + 9/25 q1, q1 <- 15 q2 - 5 q1; stage 9 sets q1 <- q2 + 3/5 q1 + dt/10 R.
-__device__ __forceinline__ void rk_store(const StageArgs &st, int64_t o, double x, double R, double r1, double r2,
-                                         double *out0, double *reg1, double *reg2) {
+// Returns the value of the state the next stage is evaluated on (RK4: S, or Q after the last
+// stage; the others: U), which the volume kernel's fused pre-pass of the next stage uses.
+__device__ __forceinline__ double rk_store(const StageArgs &st, int64_t o, double x, double R, double r1,
+                                           double r2, double *out0, double *reg1, double *reg2) {
   if (st.mode == kModeResidual) {
     out0[o] = R;
-  } else if (st.mode == kModeLSRK) {
+    return 0.0;
+  }
+  if (st.mode == kModeLSRK) {
     const double du = st.a * r1 + st.dt * R;
+    const double u = x + st.b * du;
     reg1[o] = du;
-    out0[o] = x + st.b * du;
-  } else if (st.mode == kModeRK4) {
+    out0[o] = u;
+    return u;
+  }
+  if (st.mode == kModeRK4) {
     const double acc = r1 + st.w * R;
     if (!st.last) {
+      const double sn = r2 + st.cdt * R;
       reg1[o] = acc;
-      reg2[o] = r2 + st.cdt * R;
-    } else {
-      out0[o] = r2 + st.dt * acc;
+      reg2[o] = sn;
+      return sn;
     }
-  } else {
-    if (st.stage == 9) {
-      out0[o] = r1 + 0.6 * x + st.dt / 10 * R;
-    } else {
-      const double q1 = x + st.dt / 6 * R;
-      if (st.stage == 4) {
-        const double q2 = r1 / 25 + 9.0 / 25 * q1;
-        reg1[o] = q2;
-        out0[o] = 15 * q2 - 5 * q1;
-      } else {
-        if (st.stage == 0) reg1[o] = x;
-        out0[o] = q1;
-      }
-    }
+    const double q = r2 + st.dt * acc;
+    out0[o] = q;
+    return q;
   }
+  if (st.stage == 9) {
+    const double q = r1 + 0.6 * x + st.dt / 10 * R;
+    out0[o] = q;
+    return q;
+  }
+  const double q1 = x + st.dt / 6 * R;
+  if (st.stage == 4) {
+    const double q2 = r1 / 25 + 9.0 / 25 * q1;
+    const double q = 15 * q2 - 5 * q1;
+    reg1[o] = q2;
+    out0[o] = q;
+    return q;
+  }
+  if (st.stage == 0) reg1[o] = x;
+  out0[o] = q1;
+  return q1;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -201,9 +213,11 @@ struct Cfg {
 };
 
 // Occupancy targets (waves per SIMD) per kernel and degree; 0 lets the compiler decide.
-// The volume kernel at p = 3 without the closure asks for 4: the compiler's own choice is 130
-// VGPRs (3 waves), and 128 fit without spilling (measured: the kernel 7.5% faster at 64^3).
-// Everywhere else forcing more waves than the compiler picks spills to scratch (HBM traffic).
+// The volume kernel without the closure asks for 4 at p = 3 and p = 7. At p = 3 the compiler's
+// own choice is 130 VGPRs (3 waves) and 128 fit without spilling (the kernel 7.5% faster at
+// 64^3); with the fused pre-pass (PRE) both degrees spill a few bytes per lane at 4 waves and
+// are still faster than at the compiler's 2-3 waves (measured at 64^3 p=3 and 32^3 p=7).
+// Elsewhere forcing more waves than the compiler picks spilled more and ran slower.
 #ifndef FR_WPE_PREPASS
 #define FR_WPE_PREPASS(P) 0
 #endif
@@ -211,7 +225,7 @@ struct Cfg {
 #define FR_WPE_FACE(P) 0
 #endif
 #ifndef FR_WPE_VOLUME
-#define FR_WPE_VOLUME(P, SGS) ((P) == 3 && !(SGS) ? 4 : 0)
+#define FR_WPE_VOLUME(P, SGS, PRE) (((P) == 3 || (P) == 7) && !(SGS) ? 4 : 0)
 #endif
 // The FP32 form's volume kernel at p = 7: 130 VGPRs by the compiler's choice, 128 without spill.
 #ifndef FR_WPE_VOLUME32

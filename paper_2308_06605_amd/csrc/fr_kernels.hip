@@ -262,12 +262,14 @@ __global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 // transformed divergence sum_n D_n F^n plus the flux correction
 // (s F^{I,perp} - F^d_f) g'(xi_d), R = -div/|J|, and the RK register update.
 // ------------------------------------------------------------------------------------------
-template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX>
-__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS)) void k_volume(
+// PRE: also run the next stage's pre-pass on the state this stage stores (see the end); the
+// profiles call that instance k_volume_pre.
+template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX, bool PRE>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS, PRE)) void k_volume(
     const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
     double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2,
-    const double *__restrict__ nut, real kt) {
+    const double *__restrict__ nut, real kt, real *__restrict__ face, const real *geo_again) {
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int NJ = (VISC ? 10 : 5) * NF;
@@ -459,14 +461,137 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       for (int v = 0; v < 5; ++v) div[v] += sJ[v * NF + (2 * d) * NFP + kk] * cL + sJ[v * NF + (2 * d + 1) * NFP + kk] * cR;
     }
   }
-  if (!act) return;
-  // R = -div / |J| plus the source, and the RK register update, one variable at a time
+  // R = -div / |J| plus the source, and the RK register update, one variable at a time. With
+  // PRE the stored state also goes to sU at once (nothing reads sU after the last direction's
+  // divergence), so it is not held in registers across the barrier below.
+  if (act) {
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const double R = -double(div[v]) * double(iJ) + body_force(st, Xd, v);
-    rk_store(st, base + v * NS, Xd[v], R, r1[v], r2[v], out0, reg1, reg2);
+    for (int v = 0; v < 5; ++v) {
+      const double R = -double(div[v]) * double(iJ) + body_force(st, Xd, v);
+      const double xn = rk_store(st, base + v * NS, Xd[v], R, r1[v], r2[v], out0, reg1, reg2);
+      if (PRE) sU[v * NS + t] = real(xn);
+    }
+  }
+  if (!PRE) return;
+  // The next stage's pre-pass on the state just stored (the value the next stage reads): its
+  // values and, for BR2, its broken gradient at this element's face points, with the same
+  // arithmetic as k_prepass. This saves that kernel's reads of the state; the metric terms are
+  // loaded again here (through a pointer without __restrict__, so the loads stay after the
+  // stores above and are not kept live across the divergence phase). The LDS of the divergence
+  // phase is reused: the values in sU, the gradient in sJ in chunks of VPC variables
+  // (3 VPC N_s <= 10 N_f).
+  constexpr bool GRAD = VISC && !LDG;
+  constexpr int VPC = (20 / N) < 5 ? (20 / N) : 5;
+  constexpr int UNW = P >= 6 ? 1 : VPC;  // bounds the LDS loads in flight at high degree
+  __syncthreads();
+  // face point fp of this element: the line through it along its face's normal direction runs
+  // over sU[b0 + c * stride], c = 0..N-1 (the index line_pt gives, without per-lane branches)
+  auto line = [&](int fp, int &f, int &kk, int &b0, int &stride) {
+    f = fp / NFP;
+    kk = fp - f * NFP;
+    const int a = kk % N, b = kk / N, d = f >> 1;
+    stride = d == 0 ? 1 : (d == 1 ? N : N * N);
+    b0 = d == 0 ? N * kk : (d == 1 ? a + N * N * b : kk);
+  };
+  // With a single gradient chunk (p <= 3) the gradient is formed first and the values and the
+  // gradient go to the faces in one pass, in items of five independent sums (as k_prepass);
+  // otherwise the values first, then the gradient chunk by chunk.
+  real jb[9], iJb = 0;
+  auto load_metric = [&]() {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) jb[c] = geo_again[(e * 10 + c) * NS + t];
+    iJb = geo_again[(e * 10 + 9) * NS + t];
+  };
+  // gradient components of variables v0 .. v0+nv-1 to sJ[(w * 3 + ii) * NS + t]
+  auto gradient = [&](int v0, int nv) {
+#pragma unroll UNW
+    for (int w = 0; w < VPC; ++w) {
+      if (w < nv) {
+        const int v = v0 + w;
+        real d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+          d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+          d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+        }
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          real g = jb[ii] * d0;
+          g += jb[3 + ii] * d1;
+          g += jb[6 + ii] * d2;
+          sJ[(w * 3 + ii) * NS + t] = iJb * g;
+        }
+      }
+    }
+  };
+  if (GRAD && VPC == 5) {
+    if (act) {
+      load_metric();
+      gradient(0, 5);
+    }
+    __syncthreads();
+    if (act) {
+      // items (group, face point): group 0 the values, group 1 + ii the d/dx_ii of the five
+      // variables (slot 5 + ii * 5 + v; variable v's sits at sJ[(v * 3 + ii) * NS])
+      for (int q = t; q < 4 * NF; q += NS) {
+        const int grp = q / NF;
+        int f, kk, b0, stride;
+        line(q - grp * NF, f, kk, b0, stride);
+        const bool hi = f & 1;
+        real *dst = face + ((e * 6 + f) * 20 + 5 * grp) * NFP + kk;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const real *src = grp == 0 ? &sU[v * NS] : &sJ[(v * 3 + grp - 1) * NS];
+          real acc = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * src[b0 + c * stride];
+          __builtin_nontemporal_store(acc, &dst[v * NFP]);
+        }
+      }
+    }
+    return;
+  }
+  // several chunks (p >= 4, where N_f <= N_s): items are (value, face point), which keeps
+  // more of the threads busy than one item per face point
+  if (act) {
+    for (int q = t; q < 5 * NF; q += NS) {
+      const int v = q / NF;
+      int f, kk, b0, stride;
+      line(q - v * NF, f, kk, b0, stride);
+      const bool hi = f & 1;
+      real acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sU[v * NS + b0 + c * stride];
+      __builtin_nontemporal_store(acc, &face[((e * 6 + f) * 20 + v) * NFP + kk]);
+    }
+  }
+  if (GRAD) {
+    // (the metric terms are loaded after the values pass, so they are not live across it)
+    if (act) load_metric();
+#pragma unroll
+    for (int v0 = 0; v0 < 5; v0 += VPC) {
+      const int nv = 5 - v0 < VPC ? 5 - v0 : VPC;
+      if (act) gradient(v0, nv);
+      __syncthreads();
+      if (act) {
+        for (int q = t; q < 3 * nv * NF; q += NS) {
+          const int ci = q / NF;
+          const int v = v0 + ci / 3, ii = ci - (ci / 3) * 3;
+          int f, kk, b0, stride;
+          line(q - ci * NF, f, kk, b0, stride);
+          const bool hi = f & 1;
+          real acc = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sJ[ci * NS + b0 + c * stride];
+          __builtin_nontemporal_store(acc, &face[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
+        }
+      }
+      __syncthreads();
+    }
   }
 }
+
 
 // ------------------------------------------------------------------------------------------
 // LDG: each element's corrected gradient (section "FR Algorithm", the viscous flux by the local
@@ -790,6 +915,22 @@ static int features(DeviceMesh &dm, const double *X, float *feat) {
   }
 }
 
+// Per-kernel timing accumulators of run_steps / fr_profile_stages (milliseconds and counts):
+//   [0] pre-pass ms, [1] face ms, [2] volume ms (alone), [3] stages, [4] pre-pass launches,
+//   [5] volume-with-next-pre-pass ms, [6] its launches. kTimeSlots entries.
+constexpr int kTimeSlots = 7;
+static void add_stage_times(double *ms, const float t[3], bool pre, bool vol_pre) {
+  ms[0] += t[0];
+  ms[1] += t[1];
+  if (pre) ms[4] += 1;
+  if (vol_pre) {
+    ms[5] += t[2];
+    ms[6] += 1;
+  } else {
+    ms[2] += t[2];
+  }
+}
+
 template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX, int FBS>
 static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
                           double *ms) {
@@ -813,9 +954,11 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], s));
   }
-  hipLaunchKernelGGL((k_prepass<P, real, VISC && !LDG, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
-                     (const real *)dm.geo, (real *)dm.face, dm.E, ops);
-  HIPCHK(hipGetLastError());
+  if (!st.pre_done) {
+    hipLaunchKernelGGL((k_prepass<P, real, VISC && !LDG, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s,
+                       X, (const real *)dm.geo, (real *)dm.face, dm.E, ops);
+    HIPCHK(hipGetLastError());
+  }
   if (LDG) {
     static_assert(sizeof(OpsT<double>) == sizeof(Ops1D), "operator tables share one layout");
     OpsT<double> od;
@@ -830,18 +973,22 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
                      dm.nut, kt, real(dm.ldg_tau), real(dm.wall_T / (dm.phys.gamma - 1.0)));
   HIPCHK(hipGetLastError());
   if (ms) HIPCHK(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL((k_volume<P, real, VISC, SGS, LDG, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
-                     (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1, reg2,
-                     dm.nut, kt);
+  if (st.pre_next) {
+    hipLaunchKernelGGL((k_volume<P, real, VISC, SGS, LDG, EPBX, true>), dim3((unsigned)blocks), dim3(EPBX * C::NS),
+                       0, s, X, (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1,
+                       reg2, dm.nut, kt, (real *)dm.face, (const real *)dm.geo);
+  } else {
+    hipLaunchKernelGGL((k_volume<P, real, VISC, SGS, LDG, EPBX, false>), dim3((unsigned)blocks), dim3(EPBX * C::NS),
+                       0, s, X, (const real *)dm.geo, dm.fref, (const real *)dm.fout, dm.E, ops, ph, st, out0, reg1,
+                       reg2, dm.nut, kt, (real *)nullptr, (const real *)nullptr);
+  }
   HIPCHK(hipGetLastError());
   if (ms) {
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipEventSynchronize(ev[3]));
-    for (int i = 0; i < 3; ++i) {
-      float t = 0;
-      HIPCHK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
-      ms[i] += t;
-    }
+    float t[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) HIPCHK(hipEventElapsedTime(&t[i], ev[i], ev[i + 1]));
+    add_stage_times(ms, t, !st.pre_done, st.pre_next != 0);
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
   }
   return FR_OK;
@@ -885,8 +1032,12 @@ static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o
   st.force = dm.has_force ? 1 : 0;
   for (int i = 0; i < 3; ++i) st.g[i] = dm.force[i];
   if (dm.prec == FR_FP32) {
+    // the FP32 form runs its own pre-pass in every stage
+    st.pre_done = 0;
+    st.pre_next = 0;
     std::string err;
     int rc = launch_stage32(dm, X, st, o, r1, r2, ms, err);
+    if (!rc && ms) ms[4] += 1;
     return rc ? fail(rc, err) : FR_OK;
   }
   if (dm.sgs) {
@@ -935,6 +1086,14 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
     if (rc) return rc;
   }
   (void)M;
+  // With fusion on (FP64 path) every stage but the run's first finds its pre-pass already done
+  // by the previous stage's volume kernel, and every stage but the run's last does the next
+  // one's.
+  const int n_stages = scheme == FR_LSRK45 ? 5 : (scheme == FR_RK4 ? 4 : 10);
+  auto chain = [&](StageArgs &st, int step, int s) {
+    st.pre_done = dm.fuse && !(step == 0 && s == 0);
+    st.pre_next = dm.fuse && !(step == n_steps - 1 && s == n_stages - 1);
+  };
   for (int step = 0; step < n_steps; ++step) {
     if (scheme == FR_LSRK45) {
       if (!dm.R1) {
@@ -948,6 +1107,7 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
         st.a = kLsA[s];
         st.b = kLsB[s];
         st.dt = dt;
+        chain(st, step, s);
         int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, ms_acc);
         if (rc) return rc;
         if (ms_acc) ms_acc[3] += 1;
@@ -971,6 +1131,7 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
         st.w = w[s];
         st.cdt = c[s] * dt;
         st.dt = dt;
+        chain(st, step, s);
         const double *X = s == 0 ? dm.U : dm.R2;
         int rc = launch_stage(dm, X, st, dm.U, dm.R1, dm.R2, ms_acc);
         if (rc) return rc;
@@ -986,6 +1147,7 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
         st.mode = kModeSSP;
         st.stage = s;
         st.dt = dt;
+        chain(st, step, s);
         int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, ms_acc);
         if (rc) return rc;
         if (ms_acc) ms_acc[3] += 1;
@@ -1300,22 +1462,37 @@ int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
   if (n_trials < 1) return fail(FR_ERR_ARG, "n_trials must be >= 1");
   DeviceMesh &dm = m->dm;
   const int64_t M = dm.E * 5 * dm.Ns;
-  double *tmp = nullptr;
+  // LSRK stages from the current state into scratch (the state and registers are untouched)
+  double *tmp = nullptr, *tmp2 = nullptr;
   HIPCHK(hipMalloc(&tmp, M * sizeof(double)));
+  if (hipMalloc(&tmp2, M * sizeof(double)) != hipSuccess) {
+    (void)hipFree(tmp);
+    return fail(FR_ERR_OOM, "hipMalloc of the autotuner's scratch");
+  }
   hipStream_t s = (hipStream_t)dm.stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = FR_OK;
-  double best = 1e300, t[6];
+  double best = 1e300, t[12] = {0};
   int bi = 0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FR_ERR_HIP, "hipEventCreate");
-  StageArgs st{};
-  st.mode = kModeResidual;
-  for (int c = 0; c < 6 && rc == FR_OK; ++c) {
-    dm.tile_epb = c / 3;
+  // the FP32 form has no fused pre-pass: its six "fused" entries stay 0 and are not chosen
+  const int n_choice = dm.prec == FR_FP64 ? 12 : 6;
+  for (int c = 0; c < n_choice && rc == FR_OK; ++c) {
+    dm.tile_epb = (c % 6) / 3;
     dm.tile_fbs = c % 3;
-    rc = launch_stage(dm, dm.U, st, tmp, nullptr, nullptr);  // warm-up
+    StageArgs st{};
+    st.mode = kModeLSRK;
+    st.first = 1;
+    st.a = 0.0;
+    st.b = 0.0;
+    st.dt = 0.0;
+    // c < 6: a stage with its own pre-pass; c >= 6: face + volume with the next pre-pass (the
+    // face data it reads are those the previous choice left: valid, as every choice writes them)
+    st.pre_done = c >= 6;
+    st.pre_next = c >= 6;
+    rc = launch_stage(dm, dm.U, st, tmp, tmp2, nullptr);  // warm-up
     if (rc == FR_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(FR_ERR_HIP, "hipEventRecord");
-    for (int k = 0; k < n_trials && rc == FR_OK; ++k) rc = launch_stage(dm, dm.U, st, tmp, nullptr, nullptr);
+    for (int k = 0; k < n_trials && rc == FR_OK; ++k) rc = launch_stage(dm, dm.U, st, tmp, tmp2, nullptr);
     float el = 0;
     if (rc == FR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                         hipEventElapsedTime(&el, e0, e1) != hipSuccess))
@@ -1329,11 +1506,26 @@ int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(tmp);
-  dm.tile_epb = bi / 3;
+  (void)hipFree(tmp2);
+  dm.tile_epb = (bi % 6) / 3;
   dm.tile_fbs = bi % 3;
+  if (dm.prec == FR_FP64) dm.fuse = bi >= 6;
   if (rc == FR_OK && ms)
-    for (int i = 0; i < 6; ++i) ms[i] = t[i];
+    for (int i = 0; i < 12; ++i) ms[i] = t[i];
   return rc;
+}
+
+int fr_set_fusion(fr_mesh_t m, int32_t on) {
+  if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (on != 0 && on != 1) return fail(FR_ERR_ARG, "on must be 0 or 1");
+  m->dm.fuse = on == 1;
+  return FR_OK;
+}
+
+int fr_get_fusion(fr_mesh_t m, int32_t *on) {
+  if (!valid(m) || !on) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  *on = m->dm.prec == FR_FP64 && m->dm.fuse ? 1 : 0;
+  return FR_OK;
 }
 
 int fr_set_body_force(fr_mesh_t m, const double *g) {
@@ -1563,10 +1755,14 @@ int fr_batch_destroy(fr_batch_t b) {
 
 int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms) {
   if (!valid(m) || !ms) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
-  double acc[4] = {0, 0, 0, 0};
+  double acc[kTimeSlots] = {0, 0, 0, 0, 0, 0, 0};
   int rc = run_steps(m, dt, scheme, n_steps, acc);
   if (rc) return rc;
-  for (int i = 0; i < 3; ++i) ms[i] = acc[3] > 0 ? acc[i] / acc[3] : 0;
+  const double n_alone = acc[3] - acc[6];
+  ms[0] = acc[4] > 0 ? acc[0] / acc[4] : 0;
+  ms[1] = acc[3] > 0 ? acc[1] / acc[3] : 0;
+  ms[2] = acc[6] > 0 ? acc[5] / acc[6] : 0;
+  ms[3] = n_alone > 0 ? acc[2] / n_alone : 0;
   return FR_OK;
 }
 

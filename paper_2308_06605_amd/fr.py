@@ -78,6 +78,8 @@ def load():
     L.fr_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     L.fr_get_tiles.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.fr_autotune.argtypes = [P, i32, P]
+    L.fr_set_fusion.argtypes = [P, ctypes.c_int32]
+    L.fr_get_fusion.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     L.fr_batch_create.argtypes = [P, ctypes.c_int32, P, i32, P, ctypes.POINTER(P)]
     L.fr_batch_step.argtypes = [P, i32]
     L.fr_batch_set_stream.argtypes = [P, P]
@@ -103,7 +105,7 @@ def load():
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
                  "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
                  "fr_batch_create", "fr_batch_step", "fr_batch_set_stream", "fr_batch_destroy",
-                 "fr_set_tiles", "fr_get_tiles", "fr_autotune",
+                 "fr_set_tiles", "fr_get_tiles", "fr_autotune", "fr_set_fusion", "fr_get_fusion",
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
                  "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
                  "fr_mlp_get_params", "fr_mlp_get_bf16", "fr_mlp_forward", "fr_mlp_loss_grad",
@@ -243,10 +245,13 @@ class FRMesh:
         _check(load().fr_rk_step(self.h, float(dt), SCHEME[scheme], int(n_steps)))
 
     def profile_stages(self, dt: float, scheme: str = "lsrk45", n_steps: int = 1):
-        """Mean ms per stage of (pre-pass, face, volume) kernels, from HIP events."""
-        ms = np.zeros(3)
+        """Mean kernel durations in ms from HIP events (fr_profile_stages): a dict with
+        'prepass' (per launch), 'face' (per stage), 'volume_pre' (the volume kernel that also
+        runs the next stage's pre-pass, per launch; 0 if none ran) and 'volume' (the volume
+        kernel alone, per launch)."""
+        ms = np.zeros(4)
         _check(load().fr_profile_stages(self.h, float(dt), SCHEME[scheme], int(n_steps), ms.ctypes.data))
-        return tuple(float(x) for x in ms)
+        return dict(zip(("prepass", "face", "volume_pre", "volume"), (float(x) for x in ms)))
 
     def kinetic_energy(self):
         """(E_k, dE_k/dt) of the current state, volume averaged (fr_kinetic_energy)."""
@@ -263,10 +268,21 @@ class FRMesh:
         return e.value, f.value
 
     def autotune(self, n_trials: int = 3):
-        """Time the 6 tile choices (fr_autotune); returns ((epb, fbs) chosen, ms per choice)."""
-        ms = np.zeros(6)
+        """Time the tile choices with and without the fused pre-pass (fr_autotune); returns
+        ((epb, fbs) chosen, ms per choice), ms[fuse * 6 + epb * 3 + fbs] (fusion() tells which
+        was kept; the FP32 form's fused entries are 0)."""
+        ms = np.zeros(12)
         _check(load().fr_autotune(self.h, int(n_trials), ms.ctypes.data))
         return self.tiles(), ms
+
+    def set_fusion(self, on: bool):
+        """FP64 path: each stage's volume kernel also runs the next stage's pre-pass (default)."""
+        _check(load().fr_set_fusion(self.h, 1 if on else 0))
+
+    def fusion(self) -> bool:
+        v = ctypes.c_int32()
+        _check(load().fr_get_fusion(self.h, ctypes.byref(v)))
+        return bool(v.value)
 
     def set_body_force(self, g):
         """Constant body force per unit mass (3 values; None or zeros switch it off)."""

@@ -33,9 +33,16 @@ def kernel_source_hash() -> str:
 
 
 def short_name(name: str) -> str:
-    """'void (anonymous namespace)::k_face32<3, true>(...)' -> 'k_face32'"""
+    """'void (anonymous namespace)::k_face32<3, true>(...)' -> 'k_face32'; the volume kernel's
+    instance with the fused next-stage pre-pass (last template argument true) is
+    'k_volume_pre'."""
     base = name.replace("void ", "").replace("(anonymous namespace)::", "")
-    return base.split("<")[0].split("(")[0].strip()
+    short = base.split("<")[0].split("(")[0].strip()
+    if short == "k_volume" and "<" in base:
+        targs = base.split("<", 1)[1].split(">")[0]
+        if targs.split(",")[-1].strip() in ("true", "1"):
+            return "k_volume_pre"
+    return short
 
 
 def per_kernel_kib(path: str, counter: str):

@@ -55,9 +55,37 @@ def test_autotune_picks_fastest(prec):
     g = fr.FRMesh(m, 3, mu=1e-3, flux="roe", **kw)
     g.set_state(I.state_from_coords(g.sol_coords(), I.tgv_state))
     R0 = g.residual()
+    U0 = g.get_state()
     (epb, fbs), ms = g.autotune(3)
-    print(prec, "tile timings (ms per stage):", ms, "chosen", (epb, fbs), flush=True)
-    assert np.all(ms > 0)
-    assert ms[3 * epb + fbs] == ms.min()
+    fuse = g.fusion()
+    print(prec, "tile timings (ms per stage):", ms, "chosen", (epb, fbs, fuse), flush=True)
+    n = 12 if prec == "fp64" else 6
+    assert np.all(ms[:n] > 0) and np.all(ms[n:] == 0)
+    assert ms[6 * fuse + 3 * epb + fbs] == ms[:n].min()
+    # the autotuner leaves the state and every later result as they were
+    assert np.array_equal(g.get_state(), U0)
     assert np.array_equal(g.residual(), R0)
     g.close()
+
+
+@pytest.mark.parametrize("p,scheme", [(3, "lsrk45"), (2, "rk4"), (7, "ssprk104")])
+def test_fusion_on_off_bitwise_equal(p, scheme):
+    """The fused pre-pass computes the same sums as the stand-alone one: stepping with fusion
+    on and off gives the same states bit for bit."""
+    fr = _fr()
+    m = I.box_mesh(4, q=2, curve_amp=0.04)
+    g = fr.FRMesh(m, p, mu=1e-3, flux="roe")
+    assert g.fusion()
+    X = g.sol_coords()
+    U0 = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=p, amp=0.01)
+    out = []
+    for on in (True, False):
+        g.set_fusion(on)
+        assert g.fusion() == on
+        g.set_state(U0)
+        g.rk_step(2e-4, scheme, 3)
+        out.append(g.get_state())
+    with pytest.raises(fr.FRError):
+        fr._check(fr.load().fr_set_fusion(g.h, 2))
+    g.close()
+    assert np.array_equal(out[0], out[1])
