@@ -204,7 +204,7 @@ def main():
         if args.prec == "fp32":
             kname += "32"
         rec = ts["kernels"].get(kname)
-        if ts.get("kernel_source_hash") == profiling.kernel_source_hash() and rec:
+        if ts.get("kernel_source_hash") == profiling.kernel_source_hash(args.prec) and rec:
             traffic = rec["fetch_bytes"] + rec["write_bytes"]
 
     variants = {}

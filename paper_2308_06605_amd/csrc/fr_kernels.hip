@@ -1032,12 +1032,8 @@ static int launch_stage(DeviceMesh &dm, const double *X, StageArgs st, double *o
   st.force = dm.has_force ? 1 : 0;
   for (int i = 0; i < 3; ++i) st.g[i] = dm.force[i];
   if (dm.prec == FR_FP32) {
-    // the FP32 form runs its own pre-pass in every stage
-    st.pre_done = 0;
-    st.pre_next = 0;
     std::string err;
     int rc = launch_stage32(dm, X, st, o, r1, r2, ms, err);
-    if (!rc && ms) ms[4] += 1;
     return rc ? fail(rc, err) : FR_OK;
   }
   if (dm.sgs) {

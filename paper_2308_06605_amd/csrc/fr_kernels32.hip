@@ -657,8 +657,16 @@ int launch32_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double 
 
 namespace frk {
 // Enqueue one stage of the FP32 form; returns 0 or a negative FR_ERR_* code with `err` set.
+// The FP32 form runs its own pre-pass in every stage (the stage-chaining flags are ignored);
+// ms, when given, accumulates as run_steps' timing slots ([0..2] pre-pass, face, volume ms,
+// [4] pre-pass launches).
 int launch_stage32(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
                    std::string &err) {
-  return dm.viscous ? launch32_p<true>(dm, X, st, o, r1, r2, ms, err) : launch32_p<false>(dm, X, st, o, r1, r2, ms, err);
+  st.pre_done = 0;
+  st.pre_next = 0;
+  const int rc = dm.viscous ? launch32_p<true>(dm, X, st, o, r1, r2, ms, err)
+                            : launch32_p<false>(dm, X, st, o, r1, r2, ms, err);
+  if (!rc && ms) ms[4] += 1;
+  return rc;
 }
 }  // namespace frk

@@ -21,14 +21,21 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("fr_kernels.hip", "fr_kernels32.hip", "fr_device.h", "fr_internal.h")
+# the sources each precision's stage kernels and their launchers are built from; of
+# fr_kernels.hip only the part before its C ABI section (extern "C"), which holds the kernels
+# and launchers, while the entry points after it do not change what a kernel does
+KERNEL_SOURCES = {"fp64": ("fr_kernels.hip", "fr_device.h", "fr_internal.h"),
+                  "fp32": ("fr_kernels32.hip", "fr_device.h", "fr_internal.h")}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(prec: str = "fp64") -> str:
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[prec]:
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
+            text = f.read()
+        if name == "fr_kernels.hip":
+            text = text.split(b'\nextern "C" {\n', 1)[0]
+        h.update(text)
     return h.hexdigest()[:16]
 
 
@@ -58,7 +65,7 @@ def per_kernel_kib(path: str, counter: str):
     return {key: sum(v) / len(v) for key, v in vals.items()}
 
 
-def summarize(fetch_csv: str, write_csv: str, calib_bytes: int) -> dict:
+def summarize(fetch_csv: str, write_csv: str, calib_bytes: int, prec: str = "fp64") -> dict:
     fetch = per_kernel_kib(fetch_csv, "FETCH_SIZE")
     write = per_kernel_kib(write_csv, "WRITE_SIZE")
     # the calibration copy: the copy dispatch with the largest write
@@ -77,7 +84,7 @@ def summarize(fetch_csv: str, write_csv: str, calib_bytes: int) -> dict:
             "fetch_bytes": fetch[key] * 1024.0 * f_scale,
             "write_bytes": write[key] * 1024.0 * w_scale,
         }
-    return {"kernel_source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale,
+    return {"kernel_source_hash": kernel_source_hash(prec), "prec": prec, "fetch_scale": f_scale, "write_scale": w_scale,
             "calibration_copy_bytes": calib_bytes, "kernels": kernels}
 
 
@@ -87,9 +94,10 @@ def main():
     ap.add_argument("--write", required=True)
     ap.add_argument("--calib-bytes", type=int, required=True)
     ap.add_argument("--command", default="", help="the rocprofv3 command, recorded in the summary")
+    ap.add_argument("--prec", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    s = summarize(a.fetch, a.write, a.calib_bytes)
+    s = summarize(a.fetch, a.write, a.calib_bytes, a.prec)
     s["command"] = a.command
     with open(a.out, "w") as f:
         json.dump(s, f, indent=1)
