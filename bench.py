@@ -29,6 +29,13 @@ STAGES = {"lsrk45": 5, "rk4": 4}
 KERNEL_NAMES = {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume", "volume_pre": "k_volume_pre"}
 
 
+def kernel_name(key: str, prec: str) -> str:
+    """'volume_pre', 'fp32' -> 'k_volume32_pre' (the names the profiles use)"""
+    if prec != "fp32":
+        return KERNEL_NAMES[key]
+    return "k_volume32_pre" if key == "volume_pre" else KERNEL_NAMES[key] + "32"
+
+
 def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
     """HBM bytes per element per stage that each kernel must move (every input read once,
     every output written once); the state and RK register are always FP64.
@@ -38,9 +45,10 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
                write the jump and common flux (10); per element that is 3 Nfp points
     volume   : read U (5 Ns), volume geometry (10 Ns), its faces' jumps and fluxes (10 Nf) and
                dU (5 Ns); write dU (5 Ns) and U (5 Ns)
-    volume_pre (FP64): the volume kernel that also runs the next stage's pre-pass on the state
-               it stores: the volume kernel's bytes plus the pre-pass's writes (20 Nf); its
-               reads of U and the geometry are the volume kernel's own
+    volume_pre : the volume kernel that also runs the next stage's pre-pass on the state it
+               stores: the volume kernel's bytes plus the pre-pass's writes (FP64 20 Nf doubles;
+               FP32 form 20 Nf floats + 3 Nf doubles); its reads of U and the geometry are the
+               volume kernel's own
     In the FP64 path a stage is face + volume_pre, 8 (25 Ns + 57 Nf) per element. The stage
     minimum of a two-pass design that reads its inputs in both passes is 8 (45 Ns + 44 Nf);
     `stage_min` returns that figure for the roofline of the whole stage.
@@ -61,8 +69,8 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
         k3 = 8 * 15 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
     stage_min = 8 * (45 * Ns + 44 * Nf)
     out = {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
-    if prec == "fp64":
-        out["volume_pre"] = k3 + 8 * nv * Nf
+    # the volume kernel with the next stage's pre-pass adds the pre-pass's writes
+    out["volume_pre"] = k3 + (8 * nv * Nf if prec == "fp64" else (4 * nv + 8 * 3) * Nf)
     return out
 
 
@@ -200,9 +208,7 @@ def main():
 
         with open(tfile) as f:
             ts = json.load(f)
-        kname = KERNEL_NAMES[dominant]
-        if args.prec == "fp32":
-            kname += "32"
+        kname = kernel_name(dominant, args.prec)
         rec = ts["kernels"].get(kname)
         if ts.get("kernel_source_hash") == profiling.kernel_source_hash(args.prec) and rec:
             traffic = rec["fetch_bytes"] + rec["write_bytes"]
@@ -266,7 +272,7 @@ def main():
                    "stages_per_step": stages, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": KERNEL_NAMES[dominant] + ("32" if args.prec == "fp32" else ""),
+                     "kernel": kernel_name(dominant, args.prec),
                      "bytes_per_launch": ab[dominant] * mesh.n_elem,
                      "mean_launch_ms": kms[dominant]},
         "stage": {"kernel_ms": kms, "kernel_gbs": gbs, "stage_ms": stage_ms,

@@ -152,17 +152,16 @@ int fr_get_tiles(fr_mesh_t m, int32_t *epb, int32_t *fbs);
  * (HIP events on the handle's stream, after one warm-up stage each), and keep the fastest.
  * ms (may be NULL) receives 12 mean ms per stage: index fuse * 6 + epb * 3 + fbs, where
  * fuse = 0 times the stand-alone pre-pass + face + volume kernels and fuse = 1 the face kernel
- * + the volume kernel with the next stage's pre-pass (FP32 form: fuse = 1 entries are 0 and
- * never chosen). Allocates two state-sized scratch buffers for the call; waits. The state, the
- * RK registers and the results of later calls are unaffected. */
+ * + the volume kernel with the next stage's pre-pass. Allocates two state-sized scratch
+ * buffers for the call; waits. The state, the RK registers and the results of later calls are
+ * unaffected. */
 int fr_autotune(fr_mesh_t m, int n_trials, double *ms);
 
-/* Stage chaining of the FP64 path (default on): with on = 1 each RK stage's volume kernel also
+/* Stage chaining (default on, both precisions): with on = 1 each RK stage's volume kernel also
  * computes the next stage's pre-pass (face values and broken gradient of the state it stores),
  * so a run of stages launches the stand-alone pre-pass once; with on = 0 every stage launches
  * it. The arithmetic is the same, so results are bitwise identical either way; fr_autotune
- * picks the faster. fr_get_fusion reports 0 for the FP32 form, which always uses its own
- * pre-pass. A batch captures the setting in force at its creation. */
+ * picks the faster. A batch captures the setting in force at its creation. */
 int fr_set_fusion(fr_mesh_t m, int32_t on);
 int fr_get_fusion(fr_mesh_t m, int32_t *on);
 
@@ -194,13 +193,14 @@ int fr_mesh_info(fr_mesh_t m, int64_t *n_elem, int32_t *n_sol, int64_t *device_b
 
 /* Measurement helper: run n_steps RK steps with each kernel launch bracketed by HIP events on
  * the handle's stream, and return mean durations in milliseconds (ms[4]):
- *   ms[0]  the element pre-pass, per launch. In the FP64 path a run of stages launches it once:
- *          every later stage's pre-pass is done by the previous stage's volume kernel;
+ *   ms[0]  the element pre-pass, per launch. With fusion on (fr_set_fusion) a run of stages
+ *          launches it once: every later stage's pre-pass is done by the previous stage's
+ *          volume kernel;
  *   ms[1]  the face kernel, per stage;
  *   ms[2]  the volume kernel with the RK update and the next stage's pre-pass, per launch
- *          (0 if none ran: the FP32 form, or a run of one stage);
+ *          (0 if none ran: fusion off, or a run of one stage);
  *   ms[3]  the volume kernel with the RK update alone, per launch (the run's last stage; every
- *          stage in the FP32 form).
+ *          stage with fusion off).
  * Waits for the stream. */
 int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms);
 

@@ -94,7 +94,7 @@ struct StageArgs {
   double g[3];      // body force per unit mass (source term), applied when force != 0
   int32_t force;
   int32_t pre_done;  // host: the face buffer already holds this stage's pre-pass
-  int32_t pre_next;  // the volume kernel also writes the next stage's pre-pass (FP64 path)
+  int32_t pre_next;  // the volume kernel also writes the next stage's pre-pass
   int32_t pad;
 };
 
@@ -131,7 +131,7 @@ struct DeviceMesh {
   double ref_rho = 1.0, ref_p = 0.0;
   int tile_epb = 0;             // element kernels: 0 = 256/Ns elements per block, 1 = half
   int tile_fbs = 0;             // face kernel block: 0 = 256, 1 = 128, 2 = 64 threads
-  bool fuse = true;             // FP64: each stage's volume kernel runs the next stage's pre-pass
+  bool fuse = true;             // each stage's volume kernel runs the next stage's pre-pass
   bool walls = false;           // isothermal no-slip wall faces present
   double wall_T = 1.0;          // their temperature p/rho
   bool ldg = false;             // LDG common viscous flux (else BR2)

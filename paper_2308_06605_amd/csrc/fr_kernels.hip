@@ -1082,9 +1082,8 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
     if (rc) return rc;
   }
   (void)M;
-  // With fusion on (FP64 path) every stage but the run's first finds its pre-pass already done
-  // by the previous stage's volume kernel, and every stage but the run's last does the next
-  // one's.
+  // With fusion on every stage but the run's first finds its pre-pass already done by the
+  // previous stage's volume kernel, and every stage but the run's last does the next one's.
   const int n_stages = scheme == FR_LSRK45 ? 5 : (scheme == FR_RK4 ? 4 : 10);
   auto chain = [&](StageArgs &st, int step, int s) {
     st.pre_done = dm.fuse && !(step == 0 && s == 0);
@@ -1471,9 +1470,7 @@ int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
   double best = 1e300, t[12] = {0};
   int bi = 0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FR_ERR_HIP, "hipEventCreate");
-  // the FP32 form has no fused pre-pass: its six "fused" entries stay 0 and are not chosen
-  const int n_choice = dm.prec == FR_FP64 ? 12 : 6;
-  for (int c = 0; c < n_choice && rc == FR_OK; ++c) {
+  for (int c = 0; c < 12 && rc == FR_OK; ++c) {
     dm.tile_epb = (c % 6) / 3;
     dm.tile_fbs = c % 3;
     StageArgs st{};
@@ -1505,7 +1502,7 @@ int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
   (void)hipFree(tmp2);
   dm.tile_epb = (bi % 6) / 3;
   dm.tile_fbs = bi % 3;
-  if (dm.prec == FR_FP64) dm.fuse = bi >= 6;
+  dm.fuse = bi >= 6;
   if (rc == FR_OK && ms)
     for (int i = 0; i < 12; ++i) ms[i] = t[i];
   return rc;
@@ -1520,7 +1517,7 @@ int fr_set_fusion(fr_mesh_t m, int32_t on) {
 
 int fr_get_fusion(fr_mesh_t m, int32_t *on) {
   if (!valid(m) || !on) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
-  *on = m->dm.prec == FR_FP64 && m->dm.fuse ? 1 : 0;
+  *on = m->dm.fuse ? 1 : 0;
   return FR_OK;
 }
 

@@ -333,12 +333,15 @@ __global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32
 // K3 (FP32 form): corrected gradient, reduced fluxes, divergence + correction in FP32 for
 // momentum and reduced energy, in FP64 for mass; R_E = R''_E + H_r R_rho; RK update in FP64.
 // ------------------------------------------------------------------------------------------
-template <int P, bool VISC, int EPBX>
+// PRE: also run the next stage's pre-pass (k_prepass32's outputs) on the state this stage
+// stores (see the end); the profiles call that instance k_volume32_pre.
+template <int P, bool VISC, int EPBX, bool PRE>
 __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) void k_volume32(
     const double *__restrict__ X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
     const float *__restrict__ fout32, const double *__restrict__ foutm, int64_t E, OpsT<float> ops,
     OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *__restrict__ out0,
-    double *__restrict__ reg1, double *__restrict__ reg2) {
+    double *__restrict__ reg1, double *__restrict__ reg2, float *__restrict__ face32,
+    double *__restrict__ facem, const float *geo32_again) {
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int R = (NF + NS - 1) / NS;
@@ -533,16 +536,114 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
       divm += sJm[(2 * d) * NFP + kk] * opsd.gcL[idx[d]] + sJm[(2 * d + 1) * NFP + kk] * opsd.gcR[idx[d]];
     }
   }
-  if (!act) return;
-  double Rv[5];
-  Rv[0] = -divm * iJd;
-  Rv[1] = -double(div[1]) * iJd;
-  Rv[2] = -double(div[2]) * iJd;
-  Rv[3] = -double(div[3]) * iJd;
-  Rv[4] = -double(div[4]) * iJd + ref.H_d * Rv[0];
+  // the RK update; with PRE the stored state also goes to LDS at once as U' (nothing reads sU
+  // after the last direction's divergence), and its momentum is kept for the FP64 face values
+  double xm[3] = {0, 0, 0};
+  if (act) {
+    double Rv[5];
+    Rv[0] = -divm * iJd;
+    Rv[1] = -double(div[1]) * iJd;
+    Rv[2] = -double(div[2]) * iJd;
+    Rv[3] = -double(div[3]) * iJd;
+    Rv[4] = -double(div[4]) * iJd + ref.H_d * Rv[0];
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
-    rk_store(st, base + v * NS, Xd[v], Rv[v] + body_force(st, Xd, v), r1[v], r2[v], out0, reg1, reg2);
+    for (int v = 0; v < 5; ++v) {
+      const double xn =
+          rk_store(st, base + v * NS, Xd[v], Rv[v] + body_force(st, Xd, v), r1[v], r2[v], out0, reg1, reg2);
+      if (PRE) {
+        sU[v * NS + t] = v == 0 ? float(xn - ref.rho_d) : (v == 4 ? float(xn - ref.E_d) : float(xn));
+        if (v >= 1 && v <= 3) xm[v - 1] = xn;
+      }
+    }
+  }
+  if (!PRE) return;
+  // The next stage's pre-pass on the state just stored, with the same sums as k_prepass32: U'
+  // and (viscous) its broken gradient to face32, the momentum in FP64 to facem. The LDS of the
+  // divergence phase is reused: U' in sU, one momentum component at a time in sM, the gradient
+  // in sJ in chunks of VPC variables (3 VPC N_s <= 9 N_f). Round r interpolates momentum
+  // component r (r < 3) and gradient chunk r.
+  constexpr int VPC = (18 / N) < 5 ? (18 / N) : 5;
+  constexpr int NCH = VISC ? (5 + VPC - 1) / VPC : 0;
+  constexpr int NR = NCH > 3 ? NCH : 3;
+  constexpr int UNW = P >= 6 ? 1 : VPC;  // bounds the LDS loads in flight at high degree
+  // face point fp: its line along the face normal runs over [b0 + c * stride], c = 0..N-1
+  auto line = [&](int fp, int &f, int &kk, int &b0, int &stride) {
+    f = fp / NFP;
+    kk = fp - f * NFP;
+    const int a = kk % N, b = kk / N, d = f >> 1;
+    stride = d == 0 ? 1 : (d == 1 ? N : N * N);
+    b0 = d == 0 ? N * kk : (d == 1 ? a + N * N * b : kk);
+  };
+  __syncthreads();
+  if (act) {
+    for (int q = t; q < 5 * NF; q += NS) {
+      const int v = q / NF;
+      int f, kk, b0, stride;
+      line(q - v * NF, f, kk, b0, stride);
+      const bool hi = f & 1;
+      float acc = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sU[v * NS + b0 + c * stride];
+      __builtin_nontemporal_store(acc, &face32[((e * 6 + f) * 20 + v) * NFP + kk]);
+    }
+  }
+  float jb[9], iJb = 0;
+  if (VISC && act) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) jb[c] = geo32_again[(e * 10 + c) * NS + t];
+    iJb = geo32_again[(e * 10 + 9) * NS + t];
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int v0 = r * VPC;
+    const int nv = r < NCH ? (5 - v0 < VPC ? 5 - v0 : VPC) : 0;
+    if (act) {
+      if (r < 3) sM[t] = xm[r];
+      if (VISC) {
+#pragma unroll UNW
+        for (int w = 0; w < VPC; ++w) {
+          if (w < nv) {
+            const int v = v0 + w;
+            float d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+              d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+              d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+            }
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) sJ[(w * 3 + ii) * NS + t] = iJb * (jb[ii] * d0 + jb[3 + ii] * d1 + jb[6 + ii] * d2);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      if (r < 3) {
+        for (int fp = t; fp < NF; fp += NS) {
+          int f, kk, b0, stride;
+          line(fp, f, kk, b0, stride);
+          const bool hi = f & 1;
+          double acc = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) acc += (hi ? opsd.lp[c] : opsd.lm[c]) * sM[b0 + c * stride];
+          __builtin_nontemporal_store(acc, &facem[((e * 6 + f) * 3 + r) * NFP + kk]);
+        }
+      }
+      for (int q = t; q < 3 * nv * NF; q += NS) {
+        const int ci = q / NF;
+        const int v = v0 + ci / 3, ii = ci - (ci / 3) * 3;
+        int f, kk, b0, stride;
+        line(q - ci * NF, f, kk, b0, stride);
+        const bool hi = f & 1;
+        float acc = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sJ[ci * NS + b0 + c * stride];
+        __builtin_nontemporal_store(acc, &face32[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
+      }
+    }
+    __syncthreads();
+  }
 }
 
 #define HIPCHK32(call)                                           \
@@ -593,28 +694,44 @@ int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, doub
     for (int i = 0; i < 4; ++i) HIPCHK32(hipEventCreate(&ev[i]));
     HIPCHK32(hipEventRecord(ev[0], s));
   }
-  hipLaunchKernelGGL((k_prepass32<P, VISC, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
-                     (const float *)dm.geo32,
-                     (float *)dm.face32, (double *)dm.facem, dm.E, ops, opsd, ref);
-  HIPCHK32(hipGetLastError());
+  if (!st.pre_done) {
+    hipLaunchKernelGGL((k_prepass32<P, VISC, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
+                       (const float *)dm.geo32, (float *)dm.face32, (double *)dm.facem, dm.E, ops, opsd, ref);
+    HIPCHK32(hipGetLastError());
+  }
   if (ms) HIPCHK32(hipEventRecord(ev[1], s));
   hipLaunchKernelGGL((k_face32<P, VISC, FBS>), dim3((unsigned)fblocks), dim3(FBS), 0, s, (const float *)dm.face32,
                      (const double *)dm.facem, (const double *)dm.fgeo, dm.ftab, dm.F, ph, ref, dm.flux,
                      float(tw_gm1), cw, (float *)dm.fout32, (double *)dm.foutm);
   HIPCHK32(hipGetLastError());
   if (ms) HIPCHK32(hipEventRecord(ev[2], s));
-  hipLaunchKernelGGL((k_volume32<P, VISC, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
-                     (const double *)dm.geo,
-                     dm.fref, (const float *)dm.fout32, (const double *)dm.foutm, dm.E, ops, opsd, ph, ref, st, out0,
-                     reg1, reg2);
+  if (st.pre_next) {
+    hipLaunchKernelGGL((k_volume32<P, VISC, EPBX, true>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
+                       (const double *)dm.geo, dm.fref, (const float *)dm.fout32, (const double *)dm.foutm, dm.E, ops,
+                       opsd, ph, ref, st, out0, reg1, reg2, (float *)dm.face32, (double *)dm.facem,
+                       (const float *)dm.geo32);
+  } else {
+    hipLaunchKernelGGL((k_volume32<P, VISC, EPBX, false>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
+                       (const double *)dm.geo, dm.fref, (const float *)dm.fout32, (const double *)dm.foutm, dm.E, ops,
+                       opsd, ph, ref, st, out0, reg1, reg2, (float *)nullptr, (double *)nullptr,
+                       (const float *)nullptr);
+  }
   HIPCHK32(hipGetLastError());
   if (ms) {
     HIPCHK32(hipEventRecord(ev[3], s));
     HIPCHK32(hipEventSynchronize(ev[3]));
-    for (int i = 0; i < 3; ++i) {
-      float tms = 0;
-      HIPCHK32(hipEventElapsedTime(&tms, ev[i], ev[i + 1]));
-      ms[i] += tms;
+    float tms[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) HIPCHK32(hipEventElapsedTime(&tms[i], ev[i], ev[i + 1]));
+    // run_steps' timing slots: [0] pre-pass, [1] face, [2] volume alone, [4] pre-pass launches,
+    // [5] / [6] volume with the next pre-pass (ms, launches)
+    ms[0] += tms[0];
+    ms[1] += tms[1];
+    if (!st.pre_done) ms[4] += 1;
+    if (st.pre_next) {
+      ms[5] += tms[2];
+      ms[6] += 1;
+    } else {
+      ms[2] += tms[2];
     }
     for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
   }
@@ -657,16 +774,11 @@ int launch32_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double 
 
 namespace frk {
 // Enqueue one stage of the FP32 form; returns 0 or a negative FR_ERR_* code with `err` set.
-// The FP32 form runs its own pre-pass in every stage (the stage-chaining flags are ignored);
-// ms, when given, accumulates as run_steps' timing slots ([0..2] pre-pass, face, volume ms,
-// [4] pre-pass launches).
+// StageArgs::pre_done skips the stand-alone pre-pass and StageArgs::pre_next makes the volume
+// kernel run the next stage's, as in the FP64 path; ms, when given, accumulates run_steps'
+// timing slots.
 int launch_stage32(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
                    std::string &err) {
-  st.pre_done = 0;
-  st.pre_next = 0;
-  const int rc = dm.viscous ? launch32_p<true>(dm, X, st, o, r1, r2, ms, err)
-                            : launch32_p<false>(dm, X, st, o, r1, r2, ms, err);
-  if (!rc && ms) ms[4] += 1;
-  return rc;
+  return dm.viscous ? launch32_p<true>(dm, X, st, o, r1, r2, ms, err) : launch32_p<false>(dm, X, st, o, r1, r2, ms, err);
 }
 }  // namespace frk

@@ -40,15 +40,15 @@ def kernel_source_hash(prec: str = "fp64") -> str:
 
 
 def short_name(name: str) -> str:
-    """'void (anonymous namespace)::k_face32<3, true>(...)' -> 'k_face32'; the volume kernel's
-    instance with the fused next-stage pre-pass (last template argument true) is
-    'k_volume_pre'."""
+    """'void (anonymous namespace)::k_face32<3, true>(...)' -> 'k_face32'; a volume kernel's
+    instance with the fused next-stage pre-pass (last template argument true) gets '_pre'
+    ('k_volume_pre', 'k_volume32_pre')."""
     base = name.replace("void ", "").replace("(anonymous namespace)::", "")
     short = base.split("<")[0].split("(")[0].strip()
-    if short == "k_volume" and "<" in base:
+    if short in ("k_volume", "k_volume32") and "<" in base:
         targs = base.split("<", 1)[1].split(">")[0]
         if targs.split(",")[-1].strip() in ("true", "1"):
-            return "k_volume_pre"
+            return short + "_pre"
     return short
 
 

@@ -59,22 +59,23 @@ def test_autotune_picks_fastest(prec):
     (epb, fbs), ms = g.autotune(3)
     fuse = g.fusion()
     print(prec, "tile timings (ms per stage):", ms, "chosen", (epb, fbs, fuse), flush=True)
-    n = 12 if prec == "fp64" else 6
-    assert np.all(ms[:n] > 0) and np.all(ms[n:] == 0)
-    assert ms[6 * fuse + 3 * epb + fbs] == ms[:n].min()
+    assert np.all(ms > 0)
+    assert ms[6 * fuse + 3 * epb + fbs] == ms.min()
     # the autotuner leaves the state and every later result as they were
     assert np.array_equal(g.get_state(), U0)
     assert np.array_equal(g.residual(), R0)
     g.close()
 
 
-@pytest.mark.parametrize("p,scheme", [(3, "lsrk45"), (2, "rk4"), (7, "ssprk104")])
-def test_fusion_on_off_bitwise_equal(p, scheme):
+@pytest.mark.parametrize("p,scheme,prec", [(3, "lsrk45", "fp64"), (2, "rk4", "fp64"), (7, "ssprk104", "fp64"),
+                                           (3, "lsrk45", "fp32"), (6, "rk4", "fp32")])
+def test_fusion_on_off_bitwise_equal(p, scheme, prec):
     """The fused pre-pass computes the same sums as the stand-alone one: stepping with fusion
     on and off gives the same states bit for bit."""
     fr = _fr()
     m = I.box_mesh(4, q=2, curve_amp=0.04)
-    g = fr.FRMesh(m, p, mu=1e-3, flux="roe")
+    kw = dict(prec="fp32", ref_rho=1.0, ref_p=1.0 / (1.4 * 0.01)) if prec == "fp32" else {}
+    g = fr.FRMesh(m, p, mu=1e-3, flux="roe", **kw)
     assert g.fusion()
     X = g.sol_coords()
     U0 = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=p, amp=0.01)

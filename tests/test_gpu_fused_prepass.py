@@ -1,4 +1,4 @@
-"""The volume kernel's fused pre-pass of the next stage (FP64 path).
+"""The volume kernel's fused pre-pass of the next stage (both precisions).
 
 Within one fr_rk_step call every stage after the first takes its face values and broken
 gradient from the previous stage's volume kernel (k_volume with the pre-pass tail); the first
@@ -39,18 +39,25 @@ CASES = [
     (3, "lsrk45", 0.0, "br2", None),
     (3, "lsrk45", 1e-3, "br2", "closure"),
     (3, "rk4", 1e-3, "br2", "walls"),
+    (3, "lsrk45", 1e-3, "br2", "fp32"),
+    (7, "rk4", 1e-3, "br2", "fp32"),
+    (4, "ssprk104", 0.0, "br2", "fp32"),
+    (2, "lsrk45", 1e-3, "br2", "fp32 walls"),
 ]
 
 
 @pytest.mark.parametrize("p,scheme,mu,viscous,extra", CASES)
 def test_steps_in_one_call_equal_separate_calls(p, scheme, mu, viscous, extra):
     fr = _fr()
-    if extra == "walls":
+    p0 = 1.0 / (1.4 * 0.01)
+    if extra is not None and "walls" in extra:
         m = I.box_mesh((4, 5, 4), q=2, periodic=(True, False, True), curve_amp=0.02, curve_mode="mixed")
-        kw = dict(bc_tag=I.boundary_tags(m), wall_T=1.0 / (1.4 * 0.01))
+        kw = dict(bc_tag=I.boundary_tags(m), wall_T=p0)
     else:
         m = I.box_mesh(4, q=min(p, 3), curve_amp=0.04)
         kw = {}
+    if extra is not None and "fp32" in extra:
+        kw.update(prec="fp32", ref_rho=1.0, ref_p=p0)
     g = fr.FRMesh(m, p, mu=mu, flux="roe", viscous=viscous, **kw)
     X = g.sol_coords()
     U0 = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=p, amp=0.01)
