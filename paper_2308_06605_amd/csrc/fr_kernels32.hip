@@ -345,9 +345,14 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int R = (NF + NS - 1) / NS;
-  constexpr int NJ = (VISC ? 9 : 4) * NF;  // [4][NF] flux (mom 3, reduced energy), [5][NF] jumps
+  // with the fused pre-pass at p <= 3 (SP) the tail takes one pass: sJ and sM are enlarged to
+  // hold the whole gradient (15 N_s) and the three momentum components
+  constexpr bool SP = PRE && P <= 3;
+  constexpr int NJ0 = (VISC ? 9 : 4) * NF;  // [4][NF] flux (mom 3, reduced energy), [5][NF] jumps
+  constexpr int NJ = SP && VISC && 15 * NS > NJ0 ? 15 * NS : NJ0;
+  constexpr int NMS = SP ? 3 * NS : NS;
   __shared__ float sUall[EPB][5 * NS];     // U', later 4 components of the transformed flux
-  __shared__ double sMall[EPB][NS];        // transformed mass flux of one direction
+  __shared__ double sMall[EPB][NMS];       // transformed mass flux of one direction
   __shared__ float sJall[EPB][NJ];
   __shared__ double sJmall[EPB][NF];       // mass flux along +xi_d, then its jump
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
@@ -559,8 +564,9 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
   if (!PRE) return;
   // The next stage's pre-pass on the state just stored, with the same sums as k_prepass32: U'
   // and (viscous) its broken gradient to face32, the momentum in FP64 to facem. The LDS of the
-  // divergence phase is reused: U' in sU, one momentum component at a time in sM, the gradient
-  // in sJ in chunks of VPC variables (3 VPC N_s <= 9 N_f). Round r interpolates momentum
+  // divergence phase is reused: U' in sU; at p <= 3 (SP) the momentum and gradient whole in the
+  // enlarged sM and sJ, above that one momentum component at a time in sM and the gradient in
+  // sJ in chunks of VPC variables (3 VPC N_s <= 9 N_f), round r interpolating momentum
   // component r (r < 3) and gradient chunk r.
   constexpr int VPC = (18 / N) < 5 ? (18 / N) : 5;
   constexpr int NCH = VISC ? (5 + VPC - 1) / VPC : 0;
@@ -575,6 +581,62 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
     b0 = d == 0 ? N * kk : (d == 1 ? a + N * N * b : kk);
   };
   __syncthreads();
+  if (SP) {
+    // one pass: the momentum and the whole gradient to LDS, then items (group, face point) of
+    // independent sums: group 0 U', groups 1-3 d/dx_ii of the five variables (face slot
+    // 5 + ii * 5 + v, LDS sJ[(v * 3 + ii) * N_s]), the last group the FP64 momentum
+    constexpr int NGRP = VISC ? 5 : 2;
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) sM[i * NS + t] = xm[i];
+      if (VISC) {
+        float jb[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) jb[c] = geo32_again[(e * 10 + c) * NS + t];
+        const float iJb = geo32_again[(e * 10 + 9) * NS + t];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          float d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) {
+            d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+            d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+            d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+          }
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) sJ[(v * 3 + ii) * NS + t] = iJb * (jb[ii] * d0 + jb[3 + ii] * d1 + jb[6 + ii] * d2);
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {
+      for (int q = t; q < NGRP * NF; q += NS) {
+        const int grp = q / NF;
+        int f, kk, b0, stride;
+        line(q - grp * NF, f, kk, b0, stride);
+        const bool hi = f & 1;
+        if (grp == NGRP - 1) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            double acc = 0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc += (hi ? opsd.lp[c] : opsd.lm[c]) * sM[i * NS + b0 + c * stride];
+            __builtin_nontemporal_store(acc, &facem[((e * 6 + f) * 3 + i) * NFP + kk]);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            const float *src = grp == 0 ? &sU[v * NS] : &sJ[(v * 3 + grp - 1) * NS];
+            float acc = 0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * src[b0 + c * stride];
+            __builtin_nontemporal_store(acc, &face32[((e * 6 + f) * 20 + 5 * grp + v) * NFP + kk]);
+          }
+        }
+      }
+    }
+    return;
+  }
   if (act) {
     for (int q = t; q < 5 * NF; q += NS) {
       const int v = q / NF;
