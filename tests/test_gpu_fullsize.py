@@ -3,7 +3,8 @@
 The oracle computes the residual of a random sample of elements only (its element-subset mode:
 the sample and its face neighbours), in double and in long double; the GPU computes the whole
 mesh in the same kernels the benchmark times. The RK-stage path at full size is checked by
-re-doing one LSRK45 step on the host from five GPU residuals.
+re-doing one LSRK45 step on the host from five GPU residuals; that step runs with the
+autotuned tiles and the fused pre-pass.
 """
 import numpy as np
 import pytest
@@ -34,6 +35,7 @@ def test_sampled_parity_full_size(n, p):
     X = g.sol_coords()
     U = I.state_from_coords(X, I.tgv_state)
     g.set_state(U)
+    g.autotune(2)  # the tiles the benchmark runs with
     R = g.residual()
     g.close()
     rng = np.random.default_rng(n + p)
@@ -55,6 +57,10 @@ def test_lsrk45_step_full_size_matches_residual_updates():
     g = fr.FRMesh(m, 3, mu=mu, flux="roe")
     U0 = I.state_from_coords(g.sol_coords(), I.tgv_state)
     g.set_state(U0)
+    # the launch configuration the benchmark times: autotuned tiles, and the fused pre-pass in
+    # stages 2-5 (forced on here, so the check covers it whatever the autotuner picked)
+    g.autotune(2)
+    g.set_fusion(True)
     g.rk_step(dt, "lsrk45", 1)
     Ug = g.get_state()
     A = [0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
