@@ -502,33 +502,30 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
     for (int c = 0; c < 9; ++c) jb[c] = geo_again[(e * 10 + c) * NS + t];
     iJb = geo_again[(e * 10 + 9) * NS + t];
   };
-  // gradient components of variables v0 .. v0+nv-1 to sJ[(w * 3 + ii) * NS + t]
-  auto gradient = [&](int v0, int nv) {
-#pragma unroll UNW
-    for (int w = 0; w < VPC; ++w) {
-      if (w < nv) {
-        const int v = v0 + w;
-        real d0 = 0, d1 = 0, d2 = 0;
+  // gradient components of the five variables to sJ[(v * 3 + ii) * NS + t] (single chunk)
+  auto gradient = [&]() {
 #pragma unroll
-        for (int c = 0; c < N; ++c) {
-          d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-          d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-          d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
-        }
+    for (int v = 0; v < 5; ++v) {
+      real d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          real g = jb[ii] * d0;
-          g += jb[3 + ii] * d1;
-          g += jb[6 + ii] * d2;
-          sJ[(w * 3 + ii) * NS + t] = iJb * g;
-        }
+      for (int c = 0; c < N; ++c) {
+        d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+        d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+        d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+      }
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        real g = jb[ii] * d0;
+        g += jb[3 + ii] * d1;
+        g += jb[6 + ii] * d2;
+        sJ[(v * 3 + ii) * NS + t] = iJb * g;
       }
     }
   };
   if (GRAD && VPC == 5) {
     if (act) {
       load_metric();
-      gradient(0, 5);
+      gradient();
     }
     __syncthreads();
     if (act) {
@@ -572,7 +569,30 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
 #pragma unroll
     for (int v0 = 0; v0 < 5; v0 += VPC) {
       const int nv = 5 - v0 < VPC ? 5 - v0 : VPC;
-      if (act) gradient(v0, nv);
+      // (written out rather than through gradient(): the compiler then spills 28 instead of
+      // 52 bytes per lane at p = 7)
+      if (act) {
+#pragma unroll UNW
+        for (int w = 0; w < VPC; ++w) {
+          if (w < nv) {
+            const int v = v0 + w;
+            real d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+              d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+              d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+              d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+            }
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) {
+              real g = jb[ii] * d0;
+              g += jb[3 + ii] * d1;
+              g += jb[6 + ii] * d2;
+              sJ[(w * 3 + ii) * NS + t] = iJb * g;
+            }
+          }
+        }
+      }
       __syncthreads();
       if (act) {
         for (int q = t; q < 3 * nv * NF; q += NS) {

@@ -43,6 +43,9 @@ CASES = [
     (7, "rk4", 1e-3, "br2", "fp32"),
     (4, "ssprk104", 0.0, "br2", "fp32"),
     (2, "lsrk45", 1e-3, "br2", "fp32 walls"),
+    # 75 elements: a ragged last block at every tile choice of p = 3 (4 or 2 elements per block)
+    (3, "lsrk45", 1e-3, "br2", "ragged"),
+    (3, "rk4", 1e-3, "br2", "fp32 ragged"),
 ]
 
 
@@ -53,6 +56,9 @@ def test_steps_in_one_call_equal_separate_calls(p, scheme, mu, viscous, extra):
     if extra is not None and "walls" in extra:
         m = I.box_mesh((4, 5, 4), q=2, periodic=(True, False, True), curve_amp=0.02, curve_mode="mixed")
         kw = dict(bc_tag=I.boundary_tags(m), wall_T=p0)
+    elif extra is not None and "ragged" in extra:
+        m = I.box_mesh((5, 5, 3), q=min(p, 3), curve_amp=0.04)
+        kw = {}
     else:
         m = I.box_mesh(4, q=min(p, 3), curve_amp=0.04)
         kw = {}
@@ -64,14 +70,17 @@ def test_steps_in_one_call_equal_separate_calls(p, scheme, mu, viscous, extra):
     if extra == "closure":
         g.set_eddy_viscosity(np.random.default_rng(1).uniform(0, 2e-3, m.n_elem))
     dt, n = 2e-4, 3
-    g.set_state(U0)
-    g.rk_step(dt, scheme, n)
-    A = g.get_state()
-    g.set_state(U0)
-    for _ in range(n):
-        g.rk_step(dt, scheme, 1)
-    B = g.get_state()
+    tiles = [(0, 0), (1, 1)] if extra is not None and "ragged" in extra else [g.tiles()]
+    for epb, fbs in tiles:
+        g.set_tiles(epb, fbs)
+        g.set_state(U0)
+        g.rk_step(dt, scheme, n)
+        A = g.get_state()
+        g.set_state(U0)
+        for _ in range(n):
+            g.rk_step(dt, scheme, 1)
+        B = g.get_state()
+        assert np.isfinite(A).all()
+        assert not np.array_equal(A, U0)
+        assert np.array_equal(A, B), (epb, fbs, np.abs(A - B).max())
     g.close()
-    assert np.isfinite(A).all()
-    assert not np.array_equal(A, U0)
-    assert np.array_equal(A, B), np.abs(A - B).max()
