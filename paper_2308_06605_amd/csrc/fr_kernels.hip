@@ -103,7 +103,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) v
       real acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += ell[c] * src[line_pt<N>(d, c, a, b)];
-      __builtin_nontemporal_store(acc, &dst[v * NFP]);
+      face_store<NFP>(acc, &dst[v * NFP]);
     }
   }
 }
@@ -251,8 +251,8 @@ __global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     // U^ - U_L: the mean (BR2) or the non-owner's trace (LDG)
-    __builtin_nontemporal_store(LDG ? UR[v] - UL[v] : real(0.5) * (UR[v] - UL[v]), &dst[v * NFP]);
-    __builtin_nontemporal_store(nm * (Fi[v] - Fvn[v]), &dst[(5 + v) * NFP]);
+    face_store<NFP>(LDG ? UR[v] - UL[v] : real(0.5) * (UR[v] - UL[v]), &dst[v * NFP]);
+    face_store<NFP>(nm * (Fi[v] - Fvn[v]), &dst[(5 + v) * NFP]);
   }
 }
 
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
           real acc = 0;
 #pragma unroll
           for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * src[b0 + c * stride];
-          __builtin_nontemporal_store(acc, &dst[v * NFP]);
+          face_store<NFP>(acc, &dst[v * NFP]);
         }
       }
     }
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       real acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sU[v * NS + b0 + c * stride];
-      __builtin_nontemporal_store(acc, &face[((e * 6 + f) * 20 + v) * NFP + kk]);
+      face_store<NFP>(acc, &face[((e * 6 + f) * 20 + v) * NFP + kk]);
     }
   }
   if (GRAD) {
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
           real acc = 0;
 #pragma unroll
           for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sJ[ci * NS + b0 + c * stride];
-          __builtin_nontemporal_store(acc, &face[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
+          face_store<NFP>(acc, &face[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
         }
       }
       __syncthreads();
@@ -708,7 +708,7 @@ __global__ __launch_bounds__(Cfg<P>::BLOCK) void k_ldg_grad(const double *__rest
       double acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][i * 5 + v][line_pt<N>(d, c, a, b)];
-      __builtin_nontemporal_store(acc, &dst[v * NFP]);
+      face_store<NFP>(acc, &dst[v * NFP]);
     }
   }
 }
@@ -863,7 +863,7 @@ __global__ __launch_bounds__(256) void k_kinetic(const double *__restrict__ U, c
   s[1][threadIdx.x] = b;
   s[2][threadIdx.x] = c;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (unsigned h = 128; h > 0; h >>= 1) {
     if (threadIdx.x < h)
       for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + h];
     __syncthreads();

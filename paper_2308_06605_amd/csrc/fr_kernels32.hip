@@ -183,7 +183,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *_
       float acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += ell[c] * sU[slot][v][line_pt<N>(d, c, a, b)];
-      __builtin_nontemporal_store(acc, &dst[v * NFP]);
+      face_store<NFP>(acc, &dst[v * NFP]);
     }
     if (VISC) {
 #pragma unroll 5
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *_
         float acc = 0;
 #pragma unroll
         for (int c = 0; c < N; ++c) acc += ell[c] * sG[slot][g % NG][line_pt<N>(d, c, a, b)];
-        __builtin_nontemporal_store(acc, &dst[(5 + g) * NFP]);
+        face_store<NFP>(acc, &dst[(5 + g) * NFP]);
       }
     }
     double *dm = facem + ((e * 6 + f) * 3) * NFP + kk;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *_
       double acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += elld[c] * sM[slot][i][line_pt<N>(d, c, a, b)];
-      __builtin_nontemporal_store(acc, &dm[i * NFP]);
+      face_store<NFP>(acc, &dm[i * NFP]);
     }
   }
 }
@@ -323,9 +323,9 @@ __global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32
   }
   float *dst = fout32 + (fc * 9) * NFP + kk;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(0.5f * (UR[v] - UL[v]), &dst[v * NFP]);
+  for (int v = 0; v < 5; ++v) face_store<NFP>(0.5f * (UR[v] - UL[v]), &dst[v * NFP]);
 #pragma unroll
-  for (int v = 1; v < 5; ++v) __builtin_nontemporal_store(nm * Fr[v], &dst[(4 + v) * NFP]);
+  for (int v = 1; v < 5; ++v) face_store<NFP>(nm * Fr[v], &dst[(4 + v) * NFP]);
   __builtin_nontemporal_store(fc_rho + double(nm * Fr[0]), &foutm[fc * NFP + kk]);
 }
 
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
             double acc = 0;
 #pragma unroll
             for (int c = 0; c < N; ++c) acc += (hi ? opsd.lp[c] : opsd.lm[c]) * sM[i * NS + b0 + c * stride];
-            __builtin_nontemporal_store(acc, &facem[((e * 6 + f) * 3 + i) * NFP + kk]);
+            face_store<NFP>(acc, &facem[((e * 6 + f) * 3 + i) * NFP + kk]);
           }
         } else {
 #pragma unroll
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
             float acc = 0;
 #pragma unroll
             for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * src[b0 + c * stride];
-            __builtin_nontemporal_store(acc, &face32[((e * 6 + f) * 20 + 5 * grp + v) * NFP + kk]);
+            face_store<NFP>(acc, &face32[((e * 6 + f) * 20 + 5 * grp + v) * NFP + kk]);
           }
         }
       }
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
       float acc = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sU[v * NS + b0 + c * stride];
-      __builtin_nontemporal_store(acc, &face32[((e * 6 + f) * 20 + v) * NFP + kk]);
+      face_store<NFP>(acc, &face32[((e * 6 + f) * 20 + v) * NFP + kk]);
     }
   }
   float jb[9], iJb = 0;
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
           double acc = 0;
 #pragma unroll
           for (int c = 0; c < N; ++c) acc += (hi ? opsd.lp[c] : opsd.lm[c]) * sM[b0 + c * stride];
-          __builtin_nontemporal_store(acc, &facem[((e * 6 + f) * 3 + r) * NFP + kk]);
+          face_store<NFP>(acc, &facem[((e * 6 + f) * 3 + r) * NFP + kk]);
         }
       }
       for (int q = t; q < 3 * nv * NF; q += NS) {
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
         float acc = 0;
 #pragma unroll
         for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sJ[ci * NS + b0 + c * stride];
-        __builtin_nontemporal_store(acc, &face32[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
+        face_store<NFP>(acc, &face32[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
       }
     }
     __syncthreads();
