@@ -161,3 +161,32 @@ def test_device_pointer_path():
     torch.cuda.synchronize()
     g.set_state(U)
     assert np.array_equal(Rt.cpu().numpy(), g.residual())
+
+
+def test_degenerate_calls():
+    """No elements is an argument error; zero RK steps leave the state bit for bit; the tuning
+    calls reject arguments outside their ranges."""
+    fr = _fr()
+    m = I.box_mesh(3, q=1)
+    empty = I.Mesh(elem_vert=m.elem_vert[:0].copy(), elem_nodes=m.elem_nodes[:0].copy(), q=1)
+    with pytest.raises(fr.FRError) as ei:
+        fr.FRMesh(empty, 2)
+    assert ei.value.name == "FR_ERR_ARG"
+    g = fr.FRMesh(m, 2, mu=1e-3)
+    X = g.sol_coords()
+    U = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=1, amp=0.01)
+    g.set_state(U)
+    for scheme in ("lsrk45", "rk4", "ssprk104"):
+        g.rk_step(1e-3, scheme, 0)
+        assert np.array_equal(g.get_state(), U)
+    with pytest.raises(fr.FRError) as ei:
+        g.rk_step(1e-3, "lsrk45", -1)
+    assert ei.value.name == "FR_ERR_ARG"
+    with pytest.raises(fr.FRError) as ei:
+        fr._check(fr.load().fr_autotune(g.h, 0, None))
+    assert ei.value.name == "FR_ERR_ARG"
+    with pytest.raises(fr.FRError):
+        g.set_tiles(0, 3)
+    with pytest.raises(fr.FRError):
+        fr._check(fr.load().fr_set_fusion(g.h, -1))
+    g.close()

@@ -79,6 +79,15 @@ def test_host_setup_errors():
     with pytest.raises(fr.FRError) as ei:
         fr.geometry_host(m, 9)
     assert ei.value.name == "FR_ERR_ARG"
+    # degenerate inputs: no elements; a geometry degree above max(p, 1)
+    empty = I.Mesh(elem_vert=m.elem_vert[:0].copy(), elem_nodes=m.elem_nodes[:0].copy(), q=1)
+    with pytest.raises(fr.FRError) as ei:
+        fr.geometry_host(empty, 2)
+    assert ei.value.name == "FR_ERR_ARG"
+    m3 = I.box_mesh(3, q=3)
+    with pytest.raises(fr.FRError) as ei:
+        fr.geometry_host(m3, 2)
+    assert ei.value.name == "FR_ERR_ARG"
 
 
 def test_host_setup_walls_match_oracle():
