@@ -6,7 +6,8 @@ Default workload (the scaled-up plain-FR configuration): periodic 64^3 hexahedra
 Carpenter-Kennedy five-stage RK45 with dt = 2.5e-4, FP64. One bench step is one full RK step
 (five stages); value = n_elem (p+1)^3 * stages / time.
 
-Prints one JSON line (rank 0) with the driver's fields plus `roofline` (dominant kernel, HBM
+Prints one JSON line (rank 0): metric, value, unit, timing and configuration fields, plus
+`roofline` (dominant kernel, HBM
 bound, algorithmic bytes per launch over its mean launch time measured with HIP events on the
 launch stream) and `cpu_baseline` (the CPU oracle timed on a bounded element sample).
 """
@@ -139,7 +140,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -41,7 +41,7 @@ enum fr_status {
   FR_ERR_MESH = -2,        /* invalid mesh: unpaired face, inconsistent corners, |J| <= 0 */
   FR_ERR_HIP = -3,         /* a HIP runtime call failed */
   FR_ERR_OOM = -4,         /* device allocation failed */
-  FR_ERR_UNSUPPORTED = -5, /* a valid request this build does not implement */
+  FR_ERR_UNSUPPORTED = -5, /* a valid request this library does not implement */
   FR_ERR_NONFINITE = -6    /* the residual holds a NaN or Inf (only with check_finite) */
 };
 
