@@ -345,9 +345,10 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int R = (NF + NS - 1) / NS;
-  // with the fused pre-pass at p <= 3 (SP) the tail takes one pass: sJ and sM are enlarged to
-  // hold the whole gradient (15 N_s) and the three momentum components
-  constexpr bool SP = PRE && P <= 3;
+  // with the fused pre-pass at p <= 6 (SP) the tail takes one pass: sJ and sM are enlarged to
+  // hold the whole gradient (15 N_s) and the three momentum components (measured: faster than
+  // the rounds below by 27% at p = 4 and 6% at p = 6; at p = 7 the larger LDS costs 3%)
+  constexpr bool SP = PRE && P <= 6;
   constexpr int NJ0 = (VISC ? 9 : 4) * NF;  // [4][NF] flux (mom 3, reduced energy), [5][NF] jumps
   constexpr int NJ = SP && VISC && 15 * NS > NJ0 ? 15 * NS : NJ0;
   constexpr int NMS = SP ? 3 * NS : NS;
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
   if (!PRE) return;
   // The next stage's pre-pass on the state just stored, with the same sums as k_prepass32: U'
   // and (viscous) its broken gradient to face32, the momentum in FP64 to facem. The LDS of the
-  // divergence phase is reused: U' in sU; at p <= 3 (SP) the momentum and gradient whole in the
+  // divergence phase is reused: U' in sU; at p <= 6 (SP) the momentum and gradient whole in the
   // enlarged sM and sJ, above that one momentum component at a time in sM and the gradient in
   // sJ in chunks of VPC variables (3 VPC N_s <= 9 N_f), round r interpolating momentum
   // component r (r < 3) and gradient chunk r.
