@@ -272,7 +272,11 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
     const double *__restrict__ nut, real kt, real *__restrict__ face, const real *geo_again) {
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
-  constexpr int NJ = (VISC ? 10 : 5) * NF;
+  // with the fused pre-pass (BR2) at p <= 5 the face-jump buffer is enlarged to hold the whole
+  // gradient (15 N_s), so the tail takes one pass (at p <= 3 10 N_f already holds it)
+  constexpr bool SPX = PRE && VISC && !LDG && P <= 5;
+  constexpr int NJ0 = (VISC ? 10 : 5) * NF;
+  constexpr int NJ = SPX && 15 * NS > NJ0 ? 15 * NS : NJ0;
   __shared__ real sUall[EPB][5 * NS];  // state, then the transformed flux of one direction
   __shared__ real sJall[EPB][NJ];      // [5][NF] flux along +xi_d (then its jump); [5][NF] U^C - U
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
@@ -481,7 +485,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
   // phase is reused: the values in sU, the gradient in sJ in chunks of VPC variables
   // (3 VPC N_s <= 10 N_f).
   constexpr bool GRAD = VISC && !LDG;
-  constexpr int VPC = (20 / N) < 5 ? (20 / N) : 5;
+  constexpr int VPC = SPX || (20 / N) >= 5 ? 5 : 20 / N;
   constexpr int UNW = P >= 6 ? 1 : VPC;  // bounds the LDS loads in flight at high degree
   __syncthreads();
   // face point fp of this element: the line through it along its face's normal direction runs
@@ -504,7 +508,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
   };
   // gradient components of the five variables to sJ[(v * 3 + ii) * NS + t] (single chunk)
   auto gradient = [&]() {
-#pragma unroll
+#pragma unroll UNW
     for (int v = 0; v < 5; ++v) {
       real d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
