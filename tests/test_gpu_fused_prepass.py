@@ -5,9 +5,10 @@ gradient from the previous stage's volume kernel (k_volume with the pre-pass tai
 stage of a call runs the stand-alone k_prepass. The two compute the same sums in the same
 order, so n steps in one call must equal n calls of one step bit for bit: the step boundaries
 of the second run go through k_prepass, those of the first through the fused tail. The
-parametrisation covers every tail variant: BR2 (values and gradient, in one chunk at p <= 3
-and in chunks of variables above), LDG and the Euler equations (values only), the closure,
-walls, and the three Runge-Kutta schemes (each hands a different register to the next stage).
+parametrisation covers every tail variant: BR2 (values and gradient, in one pass up to p = 5
+in FP64 and p = 6 in FP32, in chunks of variables above), LDG and the Euler equations (values
+only), the closure, walls, and the three Runge-Kutta schemes (each hands a different register
+to the next stage).
 """
 import numpy as np
 import pytest
@@ -33,7 +34,9 @@ CASES = [
     (3, "lsrk45", 1e-3, "br2", None),
     (3, "rk4", 1e-3, "br2", None),
     (2, "ssprk104", 1e-3, "br2", None),
+    (4, "rk4", 1e-3, "br2", None),
     (5, "lsrk45", 1e-3, "br2", None),
+    (6, "ssprk104", 1e-3, "br2", None),
     (7, "rk4", 1e-3, "br2", None),
     (4, "lsrk45", 1e-3, "ldg", None),
     (3, "lsrk45", 0.0, "br2", None),
