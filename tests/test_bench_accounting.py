@@ -1,0 +1,59 @@
+"""Host-side accounting behind the benchmark line (no GPU): the algorithmic bytes per element
+and stage of each kernel, written out from the buffer layouts, and the mapping from profiler
+kernel names to the bench's kernel keys.
+
+Bytes (FP64, per element and stage, N_s = (p+1)^3 points, N_f = 6 (p+1)^2 face points):
+  pre-pass   read U (5 N_s) and the metric terms (10 N_s), write 20 values per face point;
+  face       per face point read both sides' 20 values and the face geometry (4), write 10;
+             an element owns 3 faces' worth of face points;
+  volume     read U, the metric terms and the RK register (20 N_s) and its faces' results
+             (10 N_f), write the state and the register (10 N_s);
+  fused      the volume kernel's bytes plus the pre-pass's writes.
+"""
+import pytest
+
+import bench
+from paper_2308_06605_amd.profiling import short_name
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7])
+def test_fp64_bytes_from_layouts(p):
+    ns, nfp = (p + 1) ** 3, (p + 1) ** 2
+    nf = 6 * nfp
+    b = bench.algorithmic_bytes(p, "fp64")
+    assert b["prepass"] == 8 * (15 * ns + 20 * nf)
+    assert b["face"] == 8 * 3 * nfp * (2 * 20 + 4 + 10)
+    assert b["volume"] == 8 * (25 * ns + 10 * nf)
+    assert b["volume_pre"] == b["volume"] + 8 * 20 * nf
+    # a fused stage (face + fused volume) moves 8 (25 N_s + 57 N_f), a separate one 8 (40 N_s + 57 N_f)
+    assert b["face"] + b["volume_pre"] == 8 * (25 * ns + 57 * nf)
+    assert b["prepass"] + b["face"] + b["volume"] == 8 * (40 * ns + 57 * nf)
+    assert b["stage_min"] == 8 * (45 * ns + 44 * nf)
+
+
+def test_p3_figures():
+    b = bench.algorithmic_bytes(3, "fp64")
+    assert (b["prepass"], b["face"], b["volume"], b["volume_pre"]) == (23040, 20736, 20480, 35840)
+    assert (b["face"] + b["volume_pre"]) / 64 == 884.0
+    assert (b["prepass"] + b["face"] + b["volume"]) / 64 == 1004.0
+
+
+def test_fp32_fused_bytes():
+    p = 3
+    nf = 6 * (p + 1) ** 2
+    b = bench.algorithmic_bytes(p, "fp32")
+    # 20 floats + 3 doubles per face point written by the fused pre-pass
+    assert b["volume_pre"] == b["volume"] + (4 * 20 + 8 * 3) * nf
+
+
+def test_kernel_names():
+    assert short_name("void k_volume<3, double, true, false, false, 2, true>(double const*, double*)") == "k_volume_pre"
+    assert short_name("void k_volume<3, double, true, false, false, 2, false>(double const*)") == "k_volume"
+    assert short_name("void (anonymous namespace)::k_volume32<3, true, 2, true>(double const*)") == "k_volume32_pre"
+    assert short_name("void (anonymous namespace)::k_face32<3, true, 256>(float const*)") == "k_face32"
+    assert short_name("k_prepass<7, double, true, 1>") == "k_prepass"
+    for key in ("prepass", "face", "volume", "volume_pre"):
+        assert bench.kernel_name(key, "fp64") == {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume",
+                                                  "volume_pre": "k_volume_pre"}[key]
+    assert bench.kernel_name("volume_pre", "fp32") == "k_volume32_pre"
+    assert bench.kernel_name("prepass", "fp32") == "k_prepass32"
