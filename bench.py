@@ -7,9 +7,10 @@ Carpenter-Kennedy five-stage RK45 with dt = 2.5e-4, FP64. One bench step is one 
 (five stages); value = n_elem (p+1)^3 * stages / time.
 
 Prints one JSON line (rank 0): metric, value, unit, timing and configuration fields, plus
-`roofline` (dominant kernel, HBM
-bound, algorithmic bytes per launch over its mean launch time measured with HIP events on the
-launch stream) and `cpu_baseline` (the CPU oracle timed on a bounded element sample).
+`roofline` (HBM bound: the two-pass minimum bytes of one RK stage over the stage time measured
+with HIP events on the launch stream, with the dominant kernel's own bytes over its mean launch
+time as `dominant_kernel`), `variants` (the FP32 form at the same size, and 32^3 p=7 in both
+precisions, timed the same way) and `cpu_baseline` (the CPU oracle timed on bounded samples).
 """
 from __future__ import annotations
 
@@ -39,20 +40,22 @@ def kernel_name(key: str, prec: str) -> str:
 
 def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
     """HBM bytes per element per stage that each kernel must move (every input read once,
-    every output written once); the state and RK register are always FP64.
+    every output written once); the state and RK registers are always FP64.
 
     pre-pass : read U (5 Ns) and volume geometry (10 Ns); write own face data (20 Nf)
     face     : per face point read both sides' face data (2 x 20) and the face geometry (4),
                write the jump and common flux (10); per element that is 3 Nfp points
-    volume   : read U (5 Ns), volume geometry (10 Ns), its faces' jumps and fluxes (10 Nf) and
-               dU (5 Ns); write dU (5 Ns) and U (5 Ns)
+    volume   : read U (5 Ns), the volume geometry (10 Ns), its faces' jumps and fluxes (10 Nf)
+               and the RK register (5 Ns); write the register (5 Ns) and U (5 Ns): 30 Ns + 10 Nf
+               (an LSRK45 run's first stage reads no register: 25 Ns)
     volume_pre : the volume kernel that also runs the next stage's pre-pass on the state it
                stores: the volume kernel's bytes plus the pre-pass's writes (FP64 20 Nf doubles;
                FP32 form 20 Nf floats + 3 Nf doubles); its reads of U and the geometry are the
                volume kernel's own
-    In the FP64 path a stage is face + volume_pre, 8 (25 Ns + 57 Nf) per element. The stage
-    minimum of a two-pass design that reads its inputs in both passes is 8 (45 Ns + 44 Nf);
-    `stage_min` returns that figure for the roofline of the whole stage.
+    In the FP64 path a stage is face + volume_pre, 8 (30 Ns + 57 Nf) per element: 924 B/DOF at
+    p = 3. `stage_min` is the two-pass minimum of a stage that reads its inputs in both passes:
+    FP64 8 (45 Ns + 44 Nf); FP32 form (FP64 state, FP32 geometry and face data)
+    8 * 25 Ns + 4 (20 Ns + 44 Nf). The roofline of the whole stage is taken on it.
     """
     n = p + 1
     Ns, Nfp = n ** 3, n * n
@@ -61,14 +64,15 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
     if prec == "fp64":
         k1 = 8 * 5 * Ns + 8 * (10 * Ns + nv * Nf)
         k2 = 8 * 3 * Nfp * (2 * nv + 4 + 10)
-        k3 = 8 * 15 * Ns + 8 * (10 * Ns + 10 * Nf)
+        k3 = 8 * 20 * Ns + 8 * (10 * Ns + 10 * Nf)
+        stage_min = 8 * (45 * Ns + 44 * Nf)
     else:
         # FP32 form: FP32 geometry copy for the pre-pass, face data as 20 floats + 3 doubles,
         # face results as 9 floats + 1 double; the volume kernel reads FP64 geometry (mass)
         k1 = 8 * 5 * Ns + 4 * 10 * Ns + (4 * nv + 8 * 3) * Nf
         k2 = 3 * Nfp * (2 * (4 * nv + 8 * 3) + 8 * 4 + 4 * 9 + 8)
-        k3 = 8 * 15 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
-    stage_min = 8 * (45 * Ns + 44 * Nf)
+        k3 = 8 * 20 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
+        stage_min = 8 * 25 * Ns + 4 * (20 * Ns + 44 * Nf)
     out = {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
     # the volume kernel with the next stage's pre-pass adds the pre-pass's writes
     out["volume_pre"] = k3 + (8 * nv * Nf if prec == "fp64" else (4 * nv + 8 * 3) * Nf)
@@ -82,17 +86,25 @@ def make_workload(n: int, p: int, curved: bool):
     return mesh
 
 
-def cpu_baseline(mesh, p, U, mu, flux, target_s=12.0):
-    """Time the CPU oracle's residual (one RK stage's work) on a bounded element sample."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_residual_rate(mesh, p, U, mu, flux, threads, target_s, seed=0):
+    """DOF-updates/s of the oracle's residual on a random element sample sized so that one
+    evaluation takes about target_s / 3 (median of 3 after 1 warm-up)."""
     import oracle
 
-    threads = len(os.sched_getaffinity(0))
-    omp = os.environ.get("OMP_NUM_THREADS")
-    if omp:
-        threads = min(threads, int(omp))
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     E = mesh.n_elem
-    n_probe = min(E, 512)
+    n_probe = min(E, max(8, 4096 // (p + 1) ** 3))
     probe = np.sort(rng.choice(E, size=n_probe, replace=False))
     o = oracle.Oracle(mesh, p, mu=mu, flux=flux, active=probe, nthreads=threads)
     o.residual(U)  # warm-up
@@ -109,10 +121,131 @@ def cpu_baseline(mesh, p, U, mu, flux, target_s=12.0):
         o.residual(U)
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
-    dof = n_sample * (p + 1) ** 3
-    return {"value": dof / t, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"residual of {n_sample} random elements of the same mesh and state "
-                      f"(median of 3 after 1 warm-up), double precision, {threads} OpenMP threads"}
+    return n_sample * (p + 1) ** 3 / t, n_sample
+
+
+def cpu_baseline(mesh, p, U, mu, flux, extra=(), target_s=8.0):
+    """The CPU oracle timed on this host: its residual (one RK stage's work) on a bounded element
+    sample of the benchmark's mesh and state with all threads (the reported value) and with one
+    thread, a full RK4 step on 8^3 p=3, and the residual of each extra (label, mesh, p, U)."""
+    import oracle
+
+    from paper_2308_06605_amd import inputs
+
+    threads = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        threads = min(threads, int(omp))
+    rate, n_sample = _oracle_residual_rate(mesh, p, U, mu, flux, threads, target_s)
+    rate1, n1 = _oracle_residual_rate(mesh, p, U, mu, flux, 1, target_s / 3, seed=1)
+    out = {"value": rate, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"residual of {n_sample} random elements of the same mesh and state "
+                     f"(median of 3 after 1 warm-up), double precision, {threads} OpenMP threads",
+           "cpu_model": _cpu_model(),
+           "single_thread": {"value": rate1, "sample": f"residual of {n1} random elements, 1 thread"}}
+    # ora_rk_step: one RK4 step (four residuals) of the whole 8^3 p=3 TGV
+    m8 = inputs.box_mesh(8, q=1)
+    o8 = oracle.Oracle(m8, 3, mu=mu, flux="rusanov", nthreads=threads)
+    U8 = inputs.state_from_coords(o8.sol_coords(), inputs.tgv_state)
+    o8.rk_step(U8, 1e-3, "rk4", 1)
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        o8.rk_step(U8, 1e-3, "rk4", 1)
+        ts.append(time.perf_counter() - t0)
+    out["rk_step_8cubed_p3"] = {"value": 4 * m8.n_elem * 64 / float(np.median(ts)), "unit": "DOF-updates/s",
+                                "sample": "whole 8^3 p=3 TGV, one RK4 step (4 stages), median of 3"}
+    for label, m, pp, UU in extra:
+        r, ns = _oracle_residual_rate(m, pp, UU, mu, flux, threads, target_s / 2, seed=2)
+        out[label] = {"value": r, "unit": "DOF-updates/s", "sample": f"residual of {ns} random elements"}
+    return out
+
+
+def run_config(fr, inputs, n, p, prec, args, mu, curved=True):
+    """Build the curved TGV workload on n^3 elements at degree p in the given precision, pick
+    tiles (autotuner or --tiles), run the warm-up and time args.steps RK steps with HIP events on
+    the launch stream. Returns the timing record and (mesh, state) for the CPU baseline."""
+    import torch
+
+    mesh = make_workload(n, p, curved)
+    t0 = time.perf_counter()
+    p0 = 1.0 / (1.4 * 0.1 * 0.1)  # TGV reference pressure at Mach 0.1
+    g = fr.FRMesh(mesh, p, mu=mu, flux=args.flux, prec=prec, ref_rho=1.0, ref_p=p0)
+    t_setup = time.perf_counter() - t0
+    U = inputs.state_from_coords(g.sol_coords(), inputs.tgv_state)
+    g.set_state(U)
+    torch.cuda.synchronize()
+    tile_ms = None
+    if args.tiles is not None:
+        g.set_tiles(*args.tiles)
+        if args.fuse is not None:
+            g.set_fusion(bool(args.fuse))
+    else:
+        _, tile_ms = g.autotune(2)
+    tiles, fused = g.tiles(), g.fusion()
+    stages = STAGES[args.scheme]
+    for _ in range(args.warmup):
+        g.rk_step(args.dt, args.scheme, 1)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    g.rk_step(args.dt, args.scheme, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_step = e0.elapsed_time(e1) / args.steps
+    dof = mesh.n_elem * (p + 1) ** 3
+    stage_ms = ms_step / stages
+    # per-kernel mean launch durations (HIP events on the launch stream); with fusion the
+    # pre-pass runs once per run of stages and every other stage is face + volume_pre
+    kms = {k: v for k, v in g.profile_stages(args.dt, args.scheme, 2).items() if v > 0}
+    ab = algorithmic_bytes(p, prec)
+    E = mesh.n_elem
+    gbs = {k: ab[k] * E / (kms[k] * 1e-3) / 1e9 for k in kms}
+    per_stage = ("face", "volume_pre") if "volume_pre" in kms else ("prepass", "face", "volume")
+    dominant = max(per_stage, key=kms.get)
+    stage_bytes = ab["stage_min"] * E
+    stage_gbs = stage_bytes / (stage_ms * 1e-3) / 1e9
+    finite = bool(np.isfinite(g.get_state()).all())
+    g.close()
+
+    # measured HBM traffic of the stage's kernels from the committed rocprofv3 summary, only
+    # while the kernel sources still match the ones the counters were taken on
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_n{n}_p{p}_{prec}{'' if curved else '_affine'}.json")
+    if os.path.exists(tfile):
+        from paper_2308_06605_amd import profiling
+
+        with open(tfile) as f:
+            ts = json.load(f)
+        recs = [ts["kernels"].get(kernel_name(k, prec)) for k in per_stage]
+        if ts.get("kernel_source_hash") == profiling.kernel_source_hash(prec) and all(recs):
+            traffic = sum(r["fetch_bytes"] + r["write_bytes"] for r in recs)
+    return {
+        "workload": (f"TGV Ma0.1 Re1600, {'curved' if curved else 'affine'} periodic {n}^3 hex, p={p}, "
+                     f"{args.flux.capitalize()}+BR2, {args.scheme.upper()} dt={args.dt}, "
+                     f"{'FP64' if prec == 'fp64' else 'FP32 operators/fluxes, FP64 state and mass'}"),
+        "n": n, "n_elem": E, "dof": dof, "p": p, "prec": prec,
+        "value": dof * stages / (ms_step * 1e-3), "ms_per_step": ms_step, "stage_ms": stage_ms,
+        "tiles": {"elements_per_block": ("256/Ns", "half of 256/Ns")[tiles[0]],
+                  "face_block": (256, 128, 64)[tiles[1]], "fused_prepass": fused,
+                  "autotune_ms_per_stage": None if tile_ms is None else [float(x) for x in tile_ms]},
+        "roofline": {"bound": "hbm", "achieved": stage_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": stage_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": " + ".join(kernel_name(k, prec) for k in per_stage) + " (one RK stage)",
+                     "bytes_per_stage": stage_bytes,
+                     "bytes_rule": ("8 (45 Ns + 44 Nf) per element" if prec == "fp64"
+                                    else "8 * 25 Ns + 4 (20 Ns + 44 Nf) per element"),
+                     "dominant_kernel": {"kernel": kernel_name(dominant, prec),
+                                         "bytes_per_launch": ab[dominant] * E,
+                                         "mean_launch_ms": kms[dominant],
+                                         "achieved": gbs[dominant],
+                                         "frac": gbs[dominant] / HBM_PEAK_GBS}},
+        "kernel_ms": kms, "kernel_gbs": gbs, "setup_s": t_setup, "wall_s_timed": t_wall, "finite": finite,
+        "_mesh": mesh, "_U": U,
+    }
 
 
 def main():
@@ -133,14 +266,16 @@ def main():
     ap.add_argument("--fuse", type=int, choices=(0, 1), default=None,
                     help="with --tiles: the fused pre-pass on (1, the default) or off (fr_set_fusion)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-variants", action="store_true", help="skip timing the FP32 form")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other precision and degree (FP32 form at this size, 32^3 p=7 in both)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer once (a known-size "
                          "dispatch that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (one process, one device); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -149,141 +284,63 @@ def main():
 
     torch.cuda.set_device(0)
     mu = 1.0 / 1600.0
-    mesh = make_workload(args.n, args.p, not args.affine)
-    t0 = time.perf_counter()
-    p0 = 1.0 / (1.4 * 0.1 * 0.1)  # TGV reference pressure at Mach 0.1
-    g = fr.FRMesh(mesh, args.p, mu=mu, flux=args.flux, prec=args.prec, ref_rho=1.0, ref_p=p0)
-    t_setup = time.perf_counter() - t0
-    X = g.sol_coords()
-    U = inputs.state_from_coords(X, inputs.tgv_state)
-    g.set_state(U)
-    torch.cuda.synchronize()
-    # tile shapes and the fused pre-pass: the autotuner's choice on this mesh, or fixed ones
-    tile_ms = None
-    if args.tiles is not None:
-        g.set_tiles(*args.tiles)
-        if args.fuse is not None:
-            g.set_fusion(bool(args.fuse))
-    else:
-        _, tile_ms = g.autotune(2)
-    tiles = g.tiles()
-    fused = g.fusion()
-
-    stages = STAGES[args.scheme]
-    for _ in range(args.warmup):
-        g.rk_step(args.dt, args.scheme, 1)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    g.rk_step(args.dt, args.scheme, args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
-    dof = mesh.n_elem * (args.p + 1) ** 3
-    value = dof * stages / (ms_step * 1e-3)
-
-    # per-kernel mean launch durations (HIP events on the launch stream)
-    # (FP64: the pre-pass runs once per run of stages, every other stage is face + volume_pre)
-    kms = {k: v for k, v in g.profile_stages(args.dt, args.scheme, 2).items() if v > 0}
-    ab = algorithmic_bytes(args.p, args.prec)
-    gbs = {k: ab[k] * mesh.n_elem / (kms[k] * 1e-3) / 1e9 for k in kms}
-    per_stage = ("face", "volume_pre") if "volume_pre" in kms else ("prepass", "face", "volume")
-    dominant = max(per_stage, key=kms.get)
-    achieved = gbs[dominant]
-    stage_ms = ms_step / stages
-    stage_bytes = ab["stage_min"] * mesh.n_elem
-    ok = bool(np.isfinite(g.get_state()).all())
-
-    # HBM traffic of the dominant kernel from the committed rocprofv3 summary, only while the
-    # kernel sources still match the ones the counters were taken on
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_n{args.n}_p{args.p}_{args.prec}"
-                         f"{'_affine' if args.affine else ''}.json")
-    if os.path.exists(tfile):
-        from paper_2308_06605_amd import profiling
-
-        with open(tfile) as f:
-            ts = json.load(f)
-        kname = kernel_name(dominant, args.prec)
-        rec = ts["kernels"].get(kname)
-        if ts.get("kernel_source_hash") == profiling.kernel_source_hash(args.prec) and rec:
-            traffic = rec["fetch_bytes"] + rec["write_bytes"]
+    curved = not args.affine
+    main_run = run_config(fr, inputs, args.n, args.p, args.prec, args, mu, curved)
+    mesh, U = main_run.pop("_mesh"), main_run.pop("_U")
 
     variants = {}
-    if args.prec == "fp64" and not args.no_variants:
-        # the FP32 form on the same mesh and state, timed the same way
-        g.close()
-        g32 = fr.FRMesh(mesh, args.p, mu=mu, flux=args.flux, prec="fp32", ref_rho=1.0, ref_p=p0)
-        g32.set_state(U)
-        if args.tiles is None:
-            g32.autotune(2)
-        else:
-            g32.set_tiles(*args.tiles)
-        for _ in range(args.warmup):
-            g32.rk_step(args.dt, args.scheme, 1)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        g32.rk_step(args.dt, args.scheme, args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms32 = e0.elapsed_time(e1) / args.steps
-        k32 = {k: v for k, v in g32.profile_stages(args.dt, args.scheme, 2).items() if v > 0}
-        ab32 = algorithmic_bytes(args.p, "fp32")
-        variants["fp32"] = {
-            "value": dof * stages / (ms32 * 1e-3), "ms_per_step": ms32, "speedup_vs_fp64": ms_step / ms32,
-            "kernel_ms": k32,
-            "kernel_gbs": {k: ab32[k] * mesh.n_elem / (k32[k] * 1e-3) / 1e9 for k in k32},
-            "finite": bool(np.isfinite(g32.get_state()).all()),
-            "dtype": "f32 operators and fluxes, f64 state, RK registers and mass equation"}
-        g32.close()
+    p7 = None
+    if not args.no_variants:
+        other = "fp32" if args.prec == "fp64" else "fp64"
+        plan = [(other, args.n, args.p)]
+        if args.p == 3 and args.n == 64:
+            # the precision variant's p = 7 workload, 32^3 (the same 16.8M DOF), in both forms
+            plan += [("fp64", 32, 7), ("fp32", 32, 7)]
+        for prec, n, p in plan:
+            r = run_config(fr, inputs, n, p, prec, args, mu, curved)
+            m7, U7 = r.pop("_mesh"), r.pop("_U")
+            if p == 7 and p7 is None:
+                p7 = (m7, U7)
+            r["speedup_vs_fp64_same_size"] = None
+            variants[f"{prec}_n{n}_p{p}"] = r
+        runs = [main_run, *variants.values()]
+        for r in variants.values():
+            ref = [q for q in runs if (q["n"], q["p"], q["prec"]) == (r["n"], r["p"], "fp64")]
+            if r["prec"] == "fp32" and ref:
+                ref = ref[0]
+                r["speedup_vs_fp64_same_size"] = ref["ms_per_step"] / r["ms_per_step"]
 
     cpu = None
     if not args.no_cpu:
         try:
-            cpu = cpu_baseline(mesh, args.p, U, mu, args.flux)
+            extra = [("residual_32cubed_p7", p7[0], 7, p7[1])] if p7 is not None else []
+            cpu = cpu_baseline(mesh, args.p, U, mu, args.flux, extra)
         except Exception as exc:  # report, never fake
             cpu = {"error": str(exc)}
 
-    wl = (f"TGV Ma0.1 Re1600, {'curved' if not args.affine else 'affine'} periodic {args.n}^3 hex, "
-          f"p={args.p}, {args.flux.capitalize()}+BR2, {args.scheme.upper()} dt={args.dt}, "
-          f"{'FP64' if args.prec == 'fp64' else 'FP32 operators/fluxes, FP64 state and mass'}")
     out = {
         "metric": "DOF-updates/s per RK stage",
-        "value": value,
+        "value": main_run["value"],
         "unit": "DOF-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wl, "n_elem": mesh.n_elem, "dof": dof, "p": args.p,
-                   "tiles": {"elements_per_block": ("256/Ns", "half of 256/Ns")[tiles[0]],
-                             "face_block": (256, 128, 64)[tiles[1]],
-                             "fused_prepass": fused,
-                             "autotune_ms_per_stage": None if tile_ms is None else [float(x) for x in tile_ms]},
-                   "stages_per_step": stages, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel_name(dominant, args.prec),
-                     "bytes_per_launch": ab[dominant] * mesh.n_elem,
-                     "mean_launch_ms": kms[dominant]},
-        "stage": {"kernel_ms": kms, "kernel_gbs": gbs, "stage_ms": stage_ms,
-                  "stage_min_bytes": stage_bytes,
-                  "stage_min_bytes_frac_of_hbm": stage_bytes / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "config": {"workload": main_run["workload"], "n_elem": main_run["n_elem"], "dof": main_run["dof"],
+                   "p": args.p, "tiles": main_run["tiles"], "stages_per_step": STAGES[args.scheme],
+                   "parallelism": "single GPU"},
+        "roofline": main_run["roofline"],
+        "stage": {k: main_run[k] for k in ("stage_ms", "kernel_ms", "kernel_gbs")},
         "variants": variants,
         "cpu_baseline": cpu,
-        "setup_s": t_setup,
-        "wall_s_timed": t_wall,
-        "finite": ok,
+        "setup_s": main_run["setup_s"],
+        "wall_s_timed": main_run["wall_s_timed"],
+        "finite": main_run["finite"] and all(v["finite"] for v in variants.values()),
     }
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8

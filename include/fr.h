@@ -227,6 +227,16 @@ int fr_mesh_geometry_host(const fr_mesh_desc *desc, double *geo, double *fgeo, i
  * gcL = g_L'(x_a) and gcR = g_R'(x_a) of the DG-equivalent correction functions. */
 int fr_basis_host(int p, double *D, double *lm, double *lp, double *gcL, double *gcR);
 
+/* Host-only: the coefficient tables the RK stages use (section "FR Algorithm": explicit
+ * Runge-Kutta time integration). a, b: arrays of at least 5 doubles; *n_stages receives the count.
+ *   FR_LSRK45  n = 5: a = A_i, b = B_i of the 2N form dU <- A_i dU + dt R; U <- U + B_i dU
+ *              (Carpenter and Kennedy's ratios of integers, rounded to double);
+ *   FR_RK4     n = 4: a = the weights (1/6, 1/3, 1/3, 1/6), b = the node of the next stage
+ *              (1/2, 1/2, 1, then 0 after the last stage).
+ * FR_SSPRK104 has no table (its fixed fractions 1/6, 1/25, 9/25, 15, 5, 3/5 and 1/10 are in the
+ * stage epilogue): FR_ERR_ARG, as for an unknown scheme. */
+int fr_rk_coefficients(int scheme, double *a, double *b, int32_t *n_stages);
+
 /* ==========================================================================================
  * Batches: many meshes (any degrees, precisions, closures) advanced together. One RK step of
  * every mesh is captured once into a HIP graph, each mesh's stage kernels on a branch of its

@@ -59,6 +59,7 @@ def _load():
     L.ora_viscous_flux.argtypes = [f64, f64, f64, P, P, P]
     L.ora_rk_scalar.argtypes = [i32, i32, f64, f64, f64, i32, P]
     L.ora_rk_upwind.argtypes = [i32, i32, f64, i32, P]
+    L.ora_lsrk45_tables.argtypes = [P, P]
     L.ora_n_features.argtypes = [P]
     L.ora_sgs_features.argtypes = [P, P, P]
     L.ora_set_eddy_viscosity.argtypes = [P, P, f64]
@@ -237,6 +238,13 @@ def rk_scalar(scheme: str, ode: int, lam: float, y0: float, dt: float, nsteps: i
     out = np.empty(nsteps + 1)
     _load().ora_rk_scalar(SCHEME[scheme], ode, lam, y0, dt, nsteps, _ptr(out))
     return out
+
+
+def lsrk45_tables():
+    """(A[5], B[5]): the 2N-storage coefficients the oracle's LSRK45 driver uses."""
+    A, B = np.empty(5), np.empty(5)
+    _load().ora_lsrk45_tables(_ptr(A), _ptr(B))
+    return A, B
 
 
 def rk_upwind(scheme: str, u0, dt: float, nsteps: int) -> np.ndarray:

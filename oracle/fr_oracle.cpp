@@ -397,6 +397,22 @@ struct FaceLink {
 //   scheme 1: Carpenter-Kennedy five-stage fourth-order 2N-storage scheme:
 //             dU <- A_i dU + dt R(U);  U <- U + B_i dU.
 // ---------------------------------------------------------------------------------------------
+// The 2N-storage coefficients (A_i, B_i) of the Carpenter-Kennedy scheme, i = 0..4, as the
+// published ratios of integers.
+template <class T>
+void lsrk45_tables(T A[5], T B[5]) {
+  A[0] = T(0);
+  A[1] = -T(567301805773.0) / T(1357537059087.0);
+  A[2] = -T(2404267990393.0) / T(2016746695238.0);
+  A[3] = -T(3550918686646.0) / T(2091501179385.0);
+  A[4] = -T(1275806237668.0) / T(842570457699.0);
+  B[0] = T(1432997174477.0) / T(9575080441237.0);
+  B[1] = T(5161836677717.0) / T(13612068292357.0);
+  B[2] = T(1720146321549.0) / T(2090206949498.0);
+  B[3] = T(3134564353537.0) / T(4481467310338.0);
+  B[4] = T(2277821191437.0) / T(14882151754819.0);
+}
+
 template <class T>
 int rk_advance(vector<T> &U, T dt, int scheme, int nsteps,
                const std::function<void(const vector<T> &, vector<T> &)> &resid) {
@@ -414,11 +430,8 @@ int rk_advance(vector<T> &U, T dt, int scheme, int nsteps,
       }
       for (size_t i = 0; i < M; ++i) U[i] = U0[i] + dt * acc[i];
     } else if (scheme == 1) {
-      const T A[5] = {T(0), -T(567301805773.0) / T(1357537059087.0), -T(2404267990393.0) / T(2016746695238.0),
-                      -T(3550918686646.0) / T(2091501179385.0), -T(1275806237668.0) / T(842570457699.0)};
-      const T Bc[5] = {T(1432997174477.0) / T(9575080441237.0), T(5161836677717.0) / T(13612068292357.0),
-                       T(1720146321549.0) / T(2090206949498.0), T(3134564353537.0) / T(4481467310338.0),
-                       T(2277821191437.0) / T(14882151754819.0)};
+      T A[5], Bc[5];
+      lsrk45_tables<T>(A, Bc);
       vector<T> dU(M, T(0));
       for (int st = 0; st < 5; ++st) {
         resid(U, R);
@@ -1413,6 +1426,12 @@ int ora_rk_upwind(int scheme, int n, double dt, int nsteps, double *u) {
   });
   for (int j = 0; j < n; ++j) u[j] = y[j];
   return rc;
+}
+
+// The LSRK45 driver's 2N tables in double precision: A[5], B[5].
+int ora_lsrk45_tables(double *A, double *B) {
+  lsrk45_tables<double>(A, B);
+  return 0;
 }
 
 int ora_rk_scalar(int scheme, int ode, double lam, double y0, double dt, int nsteps, double *out) {

@@ -264,11 +264,13 @@ __global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 // ------------------------------------------------------------------------------------------
 // PRE: also run the next stage's pre-pass on the state this stage stores (see the end); the
 // profiles call that instance k_volume_pre.
+// X, the stage's state, is the same array as out0 (LSRK45, SSP) or reg2 (RK4 after the first
+// stage), so X, out0, reg1 and reg2 carry no __restrict__.
 template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX, bool PRE>
 __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS, PRE)) void k_volume(
-    const double *__restrict__ X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
+    const double *X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
-    double *__restrict__ out0, double *__restrict__ reg1, double *__restrict__ reg2,
+    double *out0, double *reg1, double *reg2,
     const double *__restrict__ nut, real kt, real *__restrict__ face, const real *geo_again) {
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
@@ -1083,6 +1085,11 @@ static const double kLsB[5] = {1432997174477.0 / 9575080441237.0, 5161836677717.
                                1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                                2277821191437.0 / 14882151754819.0};
 
+// Classical RK4: stage weights, and the offset of the next stage's evaluation point (c_{i+1};
+// 0 after the last stage).
+static const double kRk4W[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+static const double kRk4C[4] = {0.5, 0.5, 1.0, 0.0};
+
 // Allocate the RK registers a scheme needs (before any graph capture: capture cannot allocate).
 static int ensure_registers(DeviceMesh &dm, int scheme) {
   const int64_t M = dm.E * 5 * dm.Ns;
@@ -1140,8 +1147,7 @@ static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms
         HIPCHK(hipMalloc(&dm.R2, M * sizeof(double)));
         dm.bytes += M * sizeof(double);
       }
-      const double w[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-      const double c[4] = {0.5, 0.5, 1.0, 0.0};
+      const double *w = kRk4W, *c = kRk4C;
       for (int s = 0; s < 4; ++s) {
         StageArgs st{};
         st.mode = kModeRK4;
@@ -1315,6 +1321,27 @@ int fr_basis_host(int p, double *D, double *lm, double *lp, double *gcL, double 
     gcR[i] = o.gcR[i];
   }
   return FR_OK;
+}
+
+int fr_rk_coefficients(int scheme, double *a, double *b, int32_t *n_stages) {
+  if (!a || !b || !n_stages) return fail(FR_ERR_ARG, "NULL pointer");
+  if (scheme == FR_LSRK45) {
+    for (int i = 0; i < 5; ++i) {
+      a[i] = kLsA[i];
+      b[i] = kLsB[i];
+    }
+    *n_stages = 5;
+    return FR_OK;
+  }
+  if (scheme == FR_RK4) {
+    for (int i = 0; i < 4; ++i) {
+      a[i] = kRk4W[i];
+      b[i] = kRk4C[i];
+    }
+    *n_stages = 4;
+    return FR_OK;
+  }
+  return fail(FR_ERR_ARG, "tables exist for FR_LSRK45 and FR_RK4");
 }
 
 int fr_mesh_destroy(fr_mesh_t m) {

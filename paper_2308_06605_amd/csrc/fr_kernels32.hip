@@ -335,12 +335,14 @@ __global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32
 // ------------------------------------------------------------------------------------------
 // PRE: also run the next stage's pre-pass (k_prepass32's outputs) on the state this stage
 // stores (see the end); the profiles call that instance k_volume32_pre.
+// X, the stage's state, is the same array as out0 (LSRK45, SSP) or reg2 (RK4 after the first
+// stage), so X, out0, reg1 and reg2 carry no __restrict__.
 template <int P, bool VISC, int EPBX, bool PRE>
 __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) void k_volume32(
-    const double *__restrict__ X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
+    const double *X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
     const float *__restrict__ fout32, const double *__restrict__ foutm, int64_t E, OpsT<float> ops,
-    OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *__restrict__ out0,
-    double *__restrict__ reg1, double *__restrict__ reg2, float *__restrict__ face32,
+    OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *out0,
+    double *reg1, double *reg2, float *__restrict__ face32,
     double *__restrict__ facem, const float *geo32_again) {
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;

@@ -73,6 +73,7 @@ def load():
     L.fr_profile_stages.argtypes = [P, f64, i32, i32, P]
     L.fr_mesh_geometry_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, P, P, P, P]
     L.fr_basis_host.argtypes = [i32, P, P, P, P, P]
+    L.fr_rk_coefficients.argtypes = [i32, P, P, ctypes.POINTER(ctypes.c_int32)]
     L.fr_kinetic_energy.argtypes = [P, P]
     L.fr_set_body_force.argtypes = [P, P]
     L.fr_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
@@ -103,7 +104,7 @@ def load():
     L.fr_mlp_train_step.argtypes = [P, P, i64, i64, P, ctypes.c_float, P]
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
-                 "fr_mesh_geometry_host", "fr_basis_host", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
+                 "fr_mesh_geometry_host", "fr_basis_host", "fr_rk_coefficients", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
                  "fr_batch_create", "fr_batch_step", "fr_batch_set_stream", "fr_batch_destroy",
                  "fr_set_tiles", "fr_get_tiles", "fr_autotune", "fr_set_fusion", "fr_get_fusion",
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
@@ -118,6 +119,23 @@ def load():
 def _check(rc: int):
     if rc != FR_OK:
         raise FRError(rc, load().fr_last_error().decode())
+
+
+def _device_ptr(t, shape, dtype, device=None, what="tensor"):
+    """data_ptr() of a device tensor after checking that it is exactly what the C call reads or
+    writes (a contiguous array of `shape` and `dtype` on the handle's GPU); raises before any
+    library call otherwise."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what}: expected a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what}: on device {t.device.index}, the handle lives on device {device}")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _current_stream():
@@ -145,6 +163,13 @@ def _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, ref=
                         check_finite=int(bool(check_finite)), viscous=VISCOUS[viscous],
                         ref_rho=float(ref[0]), ref_p=float(ref[1]), ldg_tau=float(ldg_tau),
                         bc_tag=tags.ctypes.data if tags is not None else None, wall_T=float(wall_T))
+
+
+def rk_coefficients(scheme: str):
+    """The library's RK tables (fr_rk_coefficients): (a, b) numpy arrays of the scheme's stages."""
+    a, b, n = np.zeros(8), np.zeros(8), ctypes.c_int32()
+    _check(load().fr_rk_coefficients(SCHEME[scheme], a.ctypes.data, b.ctypes.data, ctypes.byref(n)))
+    return a[:n.value].copy(), b[:n.value].copy()
 
 
 def geometry_host(mesh, p: int, eta: float = 6.0, bc_tag=None):
@@ -186,6 +211,9 @@ class FRMesh:
         d = _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, check_finite, keep, (ref_rho, ref_p), viscous,
                   ldg_tau, bc_tag, wall_T)
         self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        import torch
+
+        self.device = torch.cuda.current_device()
         h = ctypes.c_void_p()
         _check(L.fr_mesh_create(ctypes.byref(d), self._stream, ctypes.byref(h)))
         self.h = h
@@ -216,16 +244,21 @@ class FRMesh:
 
     def set_state(self, U):
         if hasattr(U, "data_ptr"):  # torch tensor on the device
-            assert U.is_cuda and U.dtype.is_floating_point and U.is_contiguous() and tuple(U.shape) == self.shape
-            _check(load().fr_set_state(self.h, ctypes.c_void_p(U.data_ptr()), 1))
+            import torch
+
+            ptr = _device_ptr(U, self.shape, torch.float64, self.device, "set_state")
+            _check(load().fr_set_state(self.h, ptr, 1))
         else:
             U = np.ascontiguousarray(U, dtype=np.float64)
             assert U.shape == self.shape
             _check(load().fr_set_state(self.h, U.ctypes.data, 0))
 
     def get_state(self, out=None):
-        if out is not None and hasattr(out, "data_ptr"):
-            _check(load().fr_get_state(self.h, ctypes.c_void_p(out.data_ptr()), 1))
+        if out is not None:
+            import torch
+
+            ptr = _device_ptr(out, self.shape, torch.float64, self.device, "get_state(out)")
+            _check(load().fr_get_state(self.h, ptr, 1))
             return out
         U = np.empty(self.shape)
         _check(load().fr_get_state(self.h, U.ctypes.data, 0))
@@ -234,8 +267,10 @@ class FRMesh:
     def residual(self, out=None):
         """dU/dt of the current state: into a device tensor `out`, else returned as numpy."""
         if out is not None:
-            assert out.is_cuda and tuple(out.shape) == self.shape and out.is_contiguous()
-            _check(load().fr_residual(self.h, ctypes.c_void_p(out.data_ptr()), 1))
+            import torch
+
+            ptr = _device_ptr(out, self.shape, torch.float64, self.device, "residual(out)")
+            _check(load().fr_residual(self.h, ptr, 1))
             return out
         R = np.empty(self.shape)
         _check(load().fr_residual(self.h, R.ctypes.data, 0))
@@ -304,10 +339,9 @@ class FRMesh:
         import torch
 
         if out is None:
-            out = torch.empty((self.E, self.n_features), dtype=torch.float32, device="cuda")
-        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
-        assert tuple(out.shape) == (self.E, self.n_features)
-        _check(load().fr_sgs_features(self.h, ctypes.c_void_p(out.data_ptr())))
+            out = torch.empty((self.E, self.n_features), dtype=torch.float32, device=f"cuda:{self.device}")
+        ptr = _device_ptr(out, (self.E, self.n_features), torch.float32, self.device, "sgs_features(out)")
+        _check(load().fr_sgs_features(self.h, ptr))
         return out
 
     def set_eddy_viscosity(self, nu, prandtl_t: float = 0.9):
@@ -315,8 +349,10 @@ class FRMesh:
         if nu is None:
             _check(load().fr_set_eddy_viscosity(self.h, None, 0, prandtl_t))
         elif hasattr(nu, "data_ptr"):
-            assert nu.is_cuda and nu.is_contiguous() and tuple(nu.shape) == (self.E,)
-            _check(load().fr_set_eddy_viscosity(self.h, ctypes.c_void_p(nu.data_ptr()), 1, prandtl_t))
+            import torch
+
+            ptr = _device_ptr(nu, (self.E,), torch.float64, self.device, "set_eddy_viscosity")
+            _check(load().fr_set_eddy_viscosity(self.h, ptr, 1, prandtl_t))
         else:
             nu = np.ascontiguousarray(nu, dtype=np.float64)
             assert nu.shape == (self.E,)
@@ -393,11 +429,20 @@ class MLP:
         _check(load().fr_mlp_get_bf16(self.h, W1.ctypes.data, W2.ctypes.data, w3.ctypes.data))
         return W1, W2, w3
 
-    @staticmethod
-    def _x(X):
-        assert X.is_cuda and X.dtype.is_floating_point and X.element_size() == 4 and X.dim() == 2
-        assert X.stride(1) == 1
+    def _x(self, X):
+        import torch
+
+        if not getattr(X, "is_cuda", False) or X.dtype != torch.float32 or X.dim() != 2:
+            raise TypeError("X: expected a 2-D float32 device tensor")
+        if X.stride(1) != 1 or X.shape[1] < self.n_in or (X.shape[0] > 1 and X.stride(0) < self.n_in):
+            raise ValueError("X: rows of at least n_in contiguous float32 values expected")
         return ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), int(X.stride(0))
+
+    def _t(self, t, n, what="t"):
+        import torch
+
+        return _device_ptr(t.reshape(-1) if getattr(t, "is_cuda", False) and t.is_contiguous() else t, (n,),
+                           torch.float32, None, what)
 
     def forward(self, X, out=None):
         import torch
@@ -405,25 +450,24 @@ class MLP:
         xp, n, ld = self._x(X)
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device=X.device)
-        _check(load().fr_mlp_forward(self.h, xp, n, ld, ctypes.c_void_p(out.data_ptr())))
+        _check(load().fr_mlp_forward(self.h, xp, n, ld, self._t(out, n, "out")))
         return out
 
     def loss_grad(self, X, t):
         """(loss, gradient [n_params] float32 numpy) without updating."""
         xp, n, ld = self._x(X)
-        assert t.is_cuda and t.is_contiguous() and t.numel() == n and t.element_size() == 4
+        tp = self._t(t, n)
         g = np.empty(self.n_params, dtype=np.float32)
         loss = ctypes.c_double()
-        _check(load().fr_mlp_loss_grad(self.h, xp, n, ld, ctypes.c_void_p(t.data_ptr()), g.ctypes.data,
-                                       ctypes.byref(loss)))
+        _check(load().fr_mlp_loss_grad(self.h, xp, n, ld, tp, g.ctypes.data, ctypes.byref(loss)))
         return loss.value, g
 
     def train_step(self, X, t, lr: float, loss_out=None):
         """One Adam step; loss_out (float32 device tensor of one element) receives the loss."""
         xp, n, ld = self._x(X)
-        assert t.is_cuda and t.is_contiguous() and t.numel() == n and t.element_size() == 4
-        lp = ctypes.c_void_p(loss_out.data_ptr()) if loss_out is not None else None
-        _check(load().fr_mlp_train_step(self.h, xp, n, ld, ctypes.c_void_p(t.data_ptr()), float(lr), lp))
+        tp = self._t(t, n)
+        lp = self._t(loss_out, 1, "loss_out") if loss_out is not None else None
+        _check(load().fr_mlp_train_step(self.h, xp, n, ld, tp, float(lr), lp))
 
 
 class Batch:

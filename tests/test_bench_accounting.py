@@ -7,7 +7,7 @@ Bytes (FP64, per element and stage, N_s = (p+1)^3 points, N_f = 6 (p+1)^2 face p
   face       per face point read both sides' 20 values and the face geometry (4), write 10;
              an element owns 3 faces' worth of face points;
   volume     read U, the metric terms and the RK register (20 N_s) and its faces' results
-             (10 N_f), write the state and the register (10 N_s);
+             (10 N_f), write the state and the register (10 N_s): 30 N_s + 10 N_f;
   fused      the volume kernel's bytes plus the pre-pass's writes.
 """
 import pytest
@@ -23,19 +23,20 @@ def test_fp64_bytes_from_layouts(p):
     b = bench.algorithmic_bytes(p, "fp64")
     assert b["prepass"] == 8 * (15 * ns + 20 * nf)
     assert b["face"] == 8 * 3 * nfp * (2 * 20 + 4 + 10)
-    assert b["volume"] == 8 * (25 * ns + 10 * nf)
+    assert b["volume"] == 8 * (30 * ns + 10 * nf)
     assert b["volume_pre"] == b["volume"] + 8 * 20 * nf
-    # a fused stage (face + fused volume) moves 8 (25 N_s + 57 N_f), a separate one 8 (40 N_s + 57 N_f)
-    assert b["face"] + b["volume_pre"] == 8 * (25 * ns + 57 * nf)
-    assert b["prepass"] + b["face"] + b["volume"] == 8 * (40 * ns + 57 * nf)
+    # a fused stage (face + fused volume) moves 8 (30 N_s + 57 N_f), a separate one 8 (45 N_s + 57 N_f)
+    assert b["face"] + b["volume_pre"] == 8 * (30 * ns + 57 * nf)
+    assert b["prepass"] + b["face"] + b["volume"] == 8 * (45 * ns + 57 * nf)
     assert b["stage_min"] == 8 * (45 * ns + 44 * nf)
 
 
 def test_p3_figures():
     b = bench.algorithmic_bytes(3, "fp64")
-    assert (b["prepass"], b["face"], b["volume"], b["volume_pre"]) == (23040, 20736, 20480, 35840)
-    assert (b["face"] + b["volume_pre"]) / 64 == 884.0
-    assert (b["prepass"] + b["face"] + b["volume"]) / 64 == 1004.0
+    assert (b["prepass"], b["face"], b["volume"], b["volume_pre"]) == (23040, 20736, 23040, 38400)
+    assert (b["face"] + b["volume_pre"]) / 64 == 924.0
+    assert (b["prepass"] + b["face"] + b["volume"]) / 64 == 1044.0
+    assert b["stage_min"] / 64 == 888.0
 
 
 def test_fp32_fused_bytes():
@@ -44,6 +45,12 @@ def test_fp32_fused_bytes():
     b = bench.algorithmic_bytes(p, "fp32")
     # 20 floats + 3 doubles per face point written by the fused pre-pass
     assert b["volume_pre"] == b["volume"] + (4 * 20 + 8 * 3) * nf
+    # the FP32 form's stage minimum: FP64 state (25 N_s doubles), FP32 geometry and face data
+    ns = (p + 1) ** 3
+    assert b["stage_min"] == 8 * 25 * ns + 4 * (20 * ns + 44 * nf)
+    assert b["stage_min"] / ns == 544.0
+    assert bench.algorithmic_bytes(7, "fp32")["stage_min"] / 512 == 412.0
+    assert bench.algorithmic_bytes(7, "fp64")["stage_min"] / 512 == 624.0
 
 
 def test_kernel_names():

@@ -59,6 +59,32 @@ def test_fp32_residual_error(n, bound_var, bound_joint):
     assert joint < joint_naive / 50
 
 
+@pytest.mark.parametrize("p", [4, 5, 6, 7])
+def test_fp32_residual_error_high_degree(p):
+    """The FP32 form at p = 4..7 on a small curved (isoparametric) mesh with a perturbed TGV,
+    every element against the long-double oracle; both the separate and the fused kernels (the
+    single-pass tail up to p = 6, the rounds at p = 7) produce this residual's face data in an
+    RK run, and fused stepping is bitwise the separate one (test_gpu_fused_prepass), so the
+    residual checks the arithmetic of both."""
+    fr = _fr()
+    m = I.box_mesh(4, q=p, curve_amp=0.05)
+    g = fr.FRMesh(m, p, mu=MU, flux="roe", prec="fp32", ref_rho=1.0, ref_p=P0)
+    X = g.sol_coords()
+    U = I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=p, amp=0.01)
+    g.set_state(U)
+    R = g.residual()
+    g.close()
+    Rl = oracle.Oracle(m, p, mu=MU, flux="roe", precision="ld").residual(U)
+    e, joint = errors(R, Rl)
+    Rf = oracle.Oracle(m, p, mu=MU, flux="roe", precision="f32").residual(U)
+    _, joint_naive = errors(Rf, Rl)
+    print(f"4^3 p={p} fp32 form: per-variable {e} joint L2 {joint:.3g}; naive float {joint_naive:.3g}", flush=True)
+    assert e[0] < 1e-11, e
+    assert np.all(e < 2e-3), e
+    assert joint < 5e-4, joint
+    assert joint < joint_naive / 20
+
+
 def test_fp32_conservation():
     fr = _fr()
     p = 3

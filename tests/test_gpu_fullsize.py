@@ -2,9 +2,14 @@
 
 The oracle computes the residual of a random sample of elements only (its element-subset mode:
 the sample and its face neighbours), in double and in long double; the GPU computes the whole
-mesh in the same kernels the benchmark times. The RK-stage path at full size is checked by
-re-doing one LSRK45 step on the host from five GPU residuals; that step runs with the
-autotuned tiles and the fused pre-pass.
+mesh in the same kernels the benchmark times, with the autotuned tiles. Both precisions are
+checked this way (the FP32 form against its stated error levels). The RK-stage path is
+checked twice: a whole LSRK45 step of the 32^3 p=3 mesh (one GPU's share of the 64^3 mesh split
+over eight) against the oracle's step, and at 64^3 by re-doing the step on the host from five
+GPU residuals. Freestream preservation is checked on both curved benchmark meshes.
+
+FP64 gate: e_v <= max(1e-12, 2 f_v), f_v the double-precision oracle's own error against its
+long-double run on the same elements.
 """
 import numpy as np
 import pytest
@@ -24,6 +29,9 @@ def _fr():
 
     fr.load()
     return fr
+
+
+P0 = 1.0 / (1.4 * 0.01)
 
 
 @pytest.mark.parametrize("n,p", [(64, 3), (32, 7)])
@@ -46,7 +54,7 @@ def test_sampled_parity_full_size(n, p):
     e = np.abs(R[sample] - Rl).max(axis=(0, 2)) / scale
     f = np.abs(Ro - Rl).max(axis=(0, 2)) / scale
     print(f"{n}^3 p={p}: gpu err {e} oracle floor {f}", flush=True)
-    assert np.all(e <= np.maximum(1e-12, 4 * f)), (e, f)
+    assert np.all(e <= np.maximum(1e-12, 2 * f)), (e, f)
     assert np.isfinite(R).all()
 
 
@@ -83,3 +91,89 @@ def test_lsrk45_step_full_size_matches_residual_updates():
     err = np.abs(Ug - U).max(axis=(0, 2)) / inc
     print("lsrk45 fused vs replayed, relative to the increment:", err, flush=True)
     assert np.all(err < 1e-9), err
+
+
+# FP32 form at the benchmark sizes, per variable (max-norm over the sample relative to the
+# variable's maximum) and jointly (L2 over all variables of the sample); measured levels are
+# stated with the bounds in the test's print and the design notes.
+@pytest.mark.parametrize("n,p,bound_var,bound_joint", [(64, 3, 3e-3, 1e-3), (32, 7, 3e-3, 1e-3)])
+def test_sampled_fp32_parity_full_size(n, p, bound_var, bound_joint):
+    fr = _fr()
+    mu = 1.0 / 1600.0
+    m = I.box_mesh(n, q=p, curve_amp=0.05)
+    g = fr.FRMesh(m, p, mu=mu, flux="roe", prec="fp32", ref_rho=1.0, ref_p=P0)
+    U = I.state_from_coords(g.sol_coords(), I.tgv_state)
+    g.set_state(U)
+    tiles, _ = g.autotune(2)
+    fused = g.fusion()
+    R = g.residual()
+    g.close()
+    rng = np.random.default_rng(n + p + 1)
+    sample = np.sort(rng.choice(m.n_elem, size=96, replace=False))
+    Rl = oracle.Oracle(m, p, mu=mu, flux="roe", active=sample, precision="ld").residual(U)
+    d = R[sample] - Rl
+    e = np.abs(d).max(axis=(0, 2)) / np.abs(Rl).max(axis=(0, 2))
+    joint = np.sqrt((d ** 2).sum() / (Rl ** 2).sum())
+    print(f"{n}^3 p={p} fp32 form (tiles {tiles}, fused {fused}): per-variable {e} joint L2 {joint:.3g}",
+          flush=True)
+    assert e[0] < 1e-11, e  # the mass equation is FP64
+    assert np.all(e < bound_var), e
+    assert joint < bound_joint, joint
+
+
+def _max_flux(U):
+    """max over points and components of |F_inv,i(U)| (the inviscid flux along each axis)"""
+    rho, m, E = U[:, 0], U[:, 1:4], U[:, 4]
+    u = m / rho[:, None]
+    pr = 0.4 * (E - 0.5 * (m * u).sum(axis=1))
+    f = [np.abs(m).max()]
+    for i in range(3):
+        f.append(np.abs(m * u[:, i:i + 1] + pr[:, None] * (np.arange(3) == i)[None, :, None]).max())
+        f.append(np.abs((E + pr) * u[:, i]).max())
+    return max(f)
+
+
+@pytest.mark.parametrize("n,p", [(64, 3), (32, 7)])
+def test_freestream_full_size(n, p):
+    """A uniform flow on the curved benchmark mesh stays uniform to round-off: |R| below
+    50 eps |D_phys| max|F| with |D_phys| = |D|_inf 2/h, h = 2 pi/n (the metric terms satisfy the
+    discrete metric identity, so the residual is pure round-off of O(max|F|) fluxes)."""
+    fr = _fr()
+    m = I.box_mesh(n, q=p, curve_amp=0.05)
+    g = fr.FRMesh(m, p, mu=1.0 / 1600.0, flux="roe")
+    U = I.state_from_coords(g.sol_coords(), I.freestream_state)
+    g.set_state(U)
+    g.autotune(2)
+    R = g.residual()
+    g.close()
+    D = oracle.basis(p)["D"]
+    bound = 50 * np.finfo(np.float64).eps * np.abs(D).sum(axis=1).max() * 2 / (2 * np.pi / n) * _max_flux(U)
+    r = np.abs(R).max()
+    print(f"{n}^3 p={p} freestream: max|R| {r:.3g}, bound {bound:.3g}", flush=True)
+    assert r <= bound, (r, bound)
+
+
+def test_lsrk45_step_32cubed_matches_oracle():
+    """One fused LSRK45 step of the whole 32^3 p=3 curved TGV mesh with the autotuned tiles,
+    against the oracle's step in double and long double. Errors are measured relative to the
+    step's increment U1 - U0 per variable (a wrong coefficient or register shows at O(1)); the
+    gate is the FP64 floor rule on that measure."""
+    fr = _fr()
+    mu, dt = 1.0 / 1600.0, 2.5e-4
+    m = I.box_mesh(32, q=3, curve_amp=0.05)
+    g = fr.FRMesh(m, 3, mu=mu, flux="roe")
+    U0 = I.state_from_coords(g.sol_coords(), I.tgv_state)
+    g.set_state(U0)
+    g.autotune(2)
+    g.set_fusion(True)
+    g.set_state(U0)
+    g.rk_step(dt, "lsrk45", 1)
+    Ug = g.get_state()
+    g.close()
+    Uo = oracle.Oracle(m, 3, mu=mu, flux="roe").rk_step(U0, dt, "lsrk45", 1)
+    Ul = oracle.Oracle(m, 3, mu=mu, flux="roe", precision="ld").rk_step(U0, dt, "lsrk45", 1)
+    inc = np.abs(Ul - U0).max(axis=(0, 2))
+    e = np.abs(Ug - Ul).max(axis=(0, 2)) / inc
+    f = np.abs(Uo - Ul).max(axis=(0, 2)) / inc
+    print("32^3 p=3 lsrk45 step, relative to the increment: gpu", e, "oracle floor", f, flush=True)
+    assert np.all(e <= np.maximum(1e-12, 2 * f)), (e, f)

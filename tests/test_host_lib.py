@@ -119,3 +119,47 @@ def test_host_setup_walls_match_oracle():
         assert np.abs(fgeo[fid, :3, :].T - Nf[e, f]).max() < 1e-14 * max(1.0, np.abs(Nf).max())
     with pytest.raises(fr.FRError):
         fr.geometry_host(m, p)  # untagged boundary faces are an error
+
+
+def test_library_rk_tables_equal_the_oracles():
+    """libfr's RK coefficient tables, bit for bit: LSRK45 against the oracle's (which the order
+    conditions pin), RK4 against the classical weights and nodes."""
+    A, B = oracle.lsrk45_tables()
+    a, b = fr.rk_coefficients("lsrk45")
+    assert np.array_equal(a, A) and np.array_equal(b, B), (a - A, b - B)
+    w, c = fr.rk_coefficients("rk4")
+    assert np.array_equal(w, [1 / 6, 1 / 3, 1 / 3, 1 / 6])
+    assert np.array_equal(c, [0.5, 0.5, 1.0, 0.0])
+    with pytest.raises(fr.FRError):
+        fr.rk_coefficients("ssprk104")
+
+
+def test_device_arguments_are_checked_before_any_call():
+    """A tensor that is not a contiguous float64 array of the state's shape on the handle's GPU is
+    refused by the binding before the library would read or write through its pointer."""
+    import torch
+
+    class FakeDevice:
+        is_cuda = True
+
+        def __init__(self, dtype, shape, contiguous=True, index=0):
+            self.dtype, self.shape, self._c = dtype, shape, contiguous
+            self.device = torch.device("cpu") if index is None else type("D", (), {"index": index})()
+
+        def is_contiguous(self):
+            return self._c
+
+        def data_ptr(self):
+            raise AssertionError("the pointer must not be taken")
+
+    shape = (4, 5, 64)
+    with pytest.raises(ValueError):
+        fr._device_ptr(torch.zeros(shape, dtype=torch.float64), shape, torch.float64, 0)  # host tensor
+    with pytest.raises(TypeError):
+        fr._device_ptr(FakeDevice(torch.float32, shape), shape, torch.float64, 0)
+    with pytest.raises(ValueError):
+        fr._device_ptr(FakeDevice(torch.float64, (4, 5, 27)), shape, torch.float64, 0)
+    with pytest.raises(ValueError):
+        fr._device_ptr(FakeDevice(torch.float64, shape, contiguous=False), shape, torch.float64, 0)
+    with pytest.raises(ValueError):
+        fr._device_ptr(FakeDevice(torch.float64, shape, index=1), shape, torch.float64, 0)

@@ -76,3 +76,96 @@ def test_ssprk104_real_axis_stability():
     # ten stages of dt/6: stable much further along the negative real axis than RK4
     assert abs(oracle.rk_scalar("ssprk104", 0, -12.0, 1.0, 1.0, 200)[-1]) < 1.0
     assert abs(oracle.rk_scalar("ssprk104", 0, -16.0, 1.0, 1.0, 50)[-1]) > 1.0
+
+
+# Carpenter and Kennedy's published stage nodes c_i of the five-stage scheme, a separate set of
+# ratios from the 2N coefficients. They are rounded independently: the row sums of the tableau
+# reproduce them to 8e-12, except c_2 (3.8e-8).
+LSRK45_C = ["0", "1432997174477/9575080441237", "2526269341429/6820363266787",
+            "2006345519317/3224310063776", "2802321613138/2924317926251"]
+
+
+def _butcher_from_2n(A, B):
+    """Butcher tableau (a, b, c) of the 2N scheme dU <- A_i dU + dt R(U); U <- U + B_i dU, in
+    exact rational arithmetic on the given binary values. Stage i is evaluated at
+    U_0 + sum_j a_ij k_j with k_j = dt R of stage j; the register after stage l holds
+    sum_{j <= l} (prod_{m = j+1..l} A_m) k_j."""
+    from fractions import Fraction
+
+    A = [Fraction(x) for x in A]
+    B = [Fraction(x) for x in B]
+    s = len(A)
+
+    def weight(i_last, j):  # coefficient of k_j in U after stage i_last
+        tot = Fraction(0)
+        for l in range(j, i_last + 1):
+            prod = Fraction(1)
+            for m in range(j + 1, l + 1):
+                prod *= A[m]
+            tot += B[l] * prod
+        return tot
+
+    a = [[weight(i - 1, j) if j < i else Fraction(0) for j in range(s)] for i in range(s)]
+    b = [weight(s - 1, j) for j in range(s)]
+    c = [sum(row) for row in a]
+    return a, b, c
+
+
+def test_lsrk45_tables_satisfy_the_fourth_order_conditions():
+    """The eight order conditions of a fourth-order Runge-Kutta method (the rooted trees of
+    order <= 4), evaluated exactly on the oracle's double-precision 2N coefficients, and the
+    Butcher row sums against the published nodes c_i."""
+    from fractions import Fraction
+
+    A, B = oracle.lsrk45_tables()
+    a, b, c = _butcher_from_2n(A, B)
+    s = len(b)
+    ac = [sum(a[i][j] * c[j] for j in range(s)) for i in range(s)]
+    ac2 = [sum(a[i][j] * c[j] ** 2 for j in range(s)) for i in range(s)]
+    aac = [sum(a[i][j] * ac[j] for j in range(s)) for i in range(s)]
+    conds = {
+        "sum b = 1": (sum(b), Fraction(1)),
+        "b.c = 1/2": (sum(b[i] * c[i] for i in range(s)), Fraction(1, 2)),
+        "b.c^2 = 1/3": (sum(b[i] * c[i] ** 2 for i in range(s)), Fraction(1, 3)),
+        "b.Ac = 1/6": (sum(b[i] * ac[i] for i in range(s)), Fraction(1, 6)),
+        "b.c^3 = 1/4": (sum(b[i] * c[i] ** 3 for i in range(s)), Fraction(1, 4)),
+        "b.(c*Ac) = 1/8": (sum(b[i] * c[i] * ac[i] for i in range(s)), Fraction(1, 8)),
+        "b.Ac^2 = 1/12": (sum(b[i] * ac2[i] for i in range(s)), Fraction(1, 12)),
+        "b.AAc = 1/24": (sum(b[i] * aac[i] for i in range(s)), Fraction(1, 24)),
+    }
+    for name, (got, want) in conds.items():
+        assert abs(float(got - want)) <= 1e-11, (name, float(got - want))
+    # not fifth order: the scheme's order is exactly four
+    assert abs(float(sum(b[i] * c[i] ** 4 for i in range(s)) - Fraction(1, 5))) > 1e-6
+    for i in range(s):
+        assert abs(float(c[i] - Fraction(LSRK45_C[i]))) <= (5e-8 if i == 2 else 1e-11), (i, float(c[i]))
+
+
+def test_lsrk45_tables_catch_a_perturbed_digit():
+    """Negative control: one coefficient off in its twelfth significant digit breaks an order
+    condition by more than the 1e-11 tolerance."""
+    from fractions import Fraction
+
+    A, B = oracle.lsrk45_tables()
+    B = B.copy()
+    B[2] *= 1 + 1e-10
+    a, b, c = _butcher_from_2n(A, B)
+    assert abs(float(sum(b) - 1)) > 1e-11
+
+
+def test_lsrk45_driver_uses_its_tables():
+    """The stability polynomial the driver realises equals the one of the tableau: coefficients
+    1, 1, 1/2, 1/6, 1/24 (fourth order) and b A^3 c for z^5."""
+    import math
+
+    A, B = oracle.lsrk45_tables()
+    a, b, c = _butcher_from_2n(A, B)
+    s = len(b)
+    Ac = [sum(a[i][j] * c[j] for j in range(s)) for i in range(s)]
+    AAc = [sum(a[i][j] * Ac[j] for j in range(s)) for i in range(s)]
+    AAAc = [sum(a[i][j] * AAc[j] for j in range(s)) for i in range(s)]
+    c5 = float(sum(b[i] * AAAc[i] for i in range(s)))
+    coef = _stability_polynomial("lsrk45", 5)
+    for k in range(5):
+        assert abs(coef[k] - 1.0 / math.factorial(k)) < 1e-9, (k, coef[k])
+    assert abs(coef[5] - c5) < 1e-9, (coef[5], c5)
