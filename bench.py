@@ -97,37 +97,29 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def _oracle_residual_rate(mesh, p, U, mu, flux, threads, target_s, seed=0):
-    """DOF-updates/s of the oracle's residual on a random element sample sized so that one
-    evaluation takes about target_s / 3 (median of 3 after 1 warm-up)."""
+def _oracle_residual_rate(mesh, p, U, mu, flux, threads, n_sample):
+    """DOF-updates/s of the oracle's residual on the first n_sample elements, a slab of whole
+    element layers of the box (the oracle's subset mode also evaluates the traces of the
+    sample's face neighbours: two more layers), median of 3 evaluations after 1 warm-up."""
     import oracle
 
-    rng = np.random.default_rng(seed)
-    E = mesh.n_elem
-    n_probe = min(E, max(8, 4096 // (p + 1) ** 3))
-    probe = np.sort(rng.choice(E, size=n_probe, replace=False))
-    o = oracle.Oracle(mesh, p, mu=mu, flux=flux, active=probe, nthreads=threads)
-    o.residual(U)  # warm-up
-    t0 = time.perf_counter()
-    o.residual(U)
-    t_probe = time.perf_counter() - t0
-    n_sample = int(min(E, max(n_probe, n_probe * target_s / 3 / max(t_probe, 1e-6))))
-    sample = np.sort(rng.choice(E, size=n_sample, replace=False))
+    n = min(mesh.n_elem, int(n_sample))
+    sample = np.arange(n, dtype=np.int64)
     o = oracle.Oracle(mesh, p, mu=mu, flux=flux, active=sample, nthreads=threads)
-    o.residual(U)
+    o.residual(U)  # warm-up
     ts = []
     for _ in range(3):
         t0 = time.perf_counter()
         o.residual(U)
         ts.append(time.perf_counter() - t0)
-    t = float(np.median(ts))
-    return n_sample * (p + 1) ** 3 / t, n_sample
+    return n * (p + 1) ** 3 / float(np.median(ts)), n
 
 
-def cpu_baseline(mesh, p, U, mu, flux, extra=(), target_s=8.0):
-    """The CPU oracle timed on this host: its residual (one RK stage's work) on a bounded element
-    sample of the benchmark's mesh and state with all threads (the reported value) and with one
-    thread, a full RK4 step on 8^3 p=3, and the residual of each extra (label, mesh, p, U)."""
+def cpu_baseline(mesh, p, U, mu, flux, extra=()):
+    """The CPU oracle timed on this host: its residual (one RK stage's work) on a quarter of the
+    benchmark mesh's elements, with the benchmark's state, on all threads (the reported value)
+    and on two element layers with one thread; a full RK4 step on 8^3 p=3; and the residual of
+    each extra (label, mesh, p, U) on a quarter of its elements."""
     import oracle
 
     from paper_2308_06605_amd import inputs
@@ -136,13 +128,17 @@ def cpu_baseline(mesh, p, U, mu, flux, extra=(), target_s=8.0):
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp:
         threads = min(threads, int(omp))
-    rate, n_sample = _oracle_residual_rate(mesh, p, U, mu, flux, threads, target_s)
-    rate1, n1 = _oracle_residual_rate(mesh, p, U, mu, flux, 1, target_s / 3, seed=1)
+    E = mesh.n_elem
+    layer = round(E ** (2 / 3))  # elements per layer of the n^3 box
+    rate, n_sample = _oracle_residual_rate(mesh, p, U, mu, flux, threads, E // 4)
+    rate1, n1 = _oracle_residual_rate(mesh, p, U, mu, flux, 1, 2 * layer)
     out = {"value": rate, "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
-           "sample": f"residual of {n_sample} random elements of the same mesh and state "
-                     f"(median of 3 after 1 warm-up), double precision, {threads} OpenMP threads",
+           "sample": f"residual of the first {n_sample} elements (a quarter of the mesh, whole layers) "
+                     f"of the same mesh and state, median of 3 after 1 warm-up, double precision, "
+                     f"{threads} OpenMP threads",
            "cpu_model": _cpu_model(),
-           "single_thread": {"value": rate1, "sample": f"residual of {n1} random elements, 1 thread"}}
+           "single_thread": {"value": rate1, "sample": f"residual of the first {n1} elements (two layers), "
+                                                       f"1 thread"}}
     # ora_rk_step: one RK4 step (four residuals) of the whole 8^3 p=3 TGV
     m8 = inputs.box_mesh(8, q=1)
     o8 = oracle.Oracle(m8, 3, mu=mu, flux="rusanov", nthreads=threads)
@@ -156,8 +152,9 @@ def cpu_baseline(mesh, p, U, mu, flux, extra=(), target_s=8.0):
     out["rk_step_8cubed_p3"] = {"value": 4 * m8.n_elem * 64 / float(np.median(ts)), "unit": "DOF-updates/s",
                                 "sample": "whole 8^3 p=3 TGV, one RK4 step (4 stages), median of 3"}
     for label, m, pp, UU in extra:
-        r, ns = _oracle_residual_rate(m, pp, UU, mu, flux, threads, target_s / 2, seed=2)
-        out[label] = {"value": r, "unit": "DOF-updates/s", "sample": f"residual of {ns} random elements"}
+        r, ns = _oracle_residual_rate(m, pp, UU, mu, flux, threads, m.n_elem // 4)
+        out[label] = {"value": r, "unit": "DOF-updates/s",
+                      "sample": f"residual of the first {ns} elements (a quarter of the mesh)"}
     return out
 
 

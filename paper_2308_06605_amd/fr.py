@@ -438,11 +438,17 @@ class MLP:
             raise ValueError("X: rows of at least n_in contiguous float32 values expected")
         return ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), int(X.stride(0))
 
-    def _t(self, t, n, what="t"):
+    def _t(self, t, n, what="t", at_least=False):
+        """pointer of a contiguous float32 device vector of n values (at least n: an output the
+        call writes n values into)"""
         import torch
 
-        return _device_ptr(t.reshape(-1) if getattr(t, "is_cuda", False) and t.is_contiguous() else t, (n,),
-                           torch.float32, None, what)
+        if getattr(t, "is_cuda", False) and t.is_contiguous():
+            t = t.reshape(-1)
+            if at_least and t.numel() >= n:
+                t = t[:n] if n > 0 else t
+                return _device_ptr(t, (t.numel(),), torch.float32, None, what)
+        return _device_ptr(t, (n,), torch.float32, None, what)
 
     def forward(self, X, out=None):
         import torch
@@ -450,7 +456,7 @@ class MLP:
         xp, n, ld = self._x(X)
         if out is None:
             out = torch.empty(n, dtype=torch.float32, device=X.device)
-        _check(load().fr_mlp_forward(self.h, xp, n, ld, self._t(out, n, "out")))
+        _check(load().fr_mlp_forward(self.h, xp, n, ld, self._t(out, n, "out", at_least=True)))
         return out
 
     def loss_grad(self, X, t):

@@ -6,6 +6,7 @@ variable's maximum) and jointly (L2 over all variables), and bounded here at the
 measured on MI355X with margin:
   8^3 p=3 TGV:  joint L2 ~1.1e-5, per variable <= 1e-4 (momentum)
   16^3 p=3 TGV: joint L2 ~5e-5,  per variable <= 2.4e-4
+  4^3 p=4..7 perturbed TGV: joint L2 <= 1.2e-6, per variable <= 2.2e-4
 This is the FP32 round-off of O(1) fluxes differentiated at 2/h: 1e-5 per variable is below
 the FP32 floor of this Mach 0.1 workload. The split is what makes it usable at all: demoting
 the state as it is (the float oracle) is off by 0.4 % to 2 %.
@@ -79,10 +80,12 @@ def test_fp32_residual_error_high_degree(p):
     Rf = oracle.Oracle(m, p, mu=MU, flux="roe", precision="f32").residual(U)
     _, joint_naive = errors(Rf, Rl)
     print(f"4^3 p={p} fp32 form: per-variable {e} joint L2 {joint:.3g}; naive float {joint_naive:.3g}", flush=True)
-    assert e[0] < 1e-11, e
-    assert np.all(e < 2e-3), e
-    assert joint < 5e-4, joint
-    assert joint < joint_naive / 20
+    # measured on MI355X: per variable <= 2.2e-4 (momentum, p = 7), joint L2 <= 1.2e-6; the
+    # mass residual's error (1e-6 to 5e-6 of its maximum) is the Roe dissipation's, which is
+    # formed in FP32 like the other interface terms
+    assert np.all(e < 6e-4), e
+    assert joint < 4e-6, joint
+    assert joint < joint_naive / 50
 
 
 def test_fp32_conservation():
