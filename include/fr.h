@@ -341,6 +341,19 @@ int fr_mlp_loss_grad(fr_mlp_t net, const float *X, int64_t n, int64_t ldx, const
  * the update. Enqueued on the network's stream. */
 int fr_mlp_train_step(fr_mlp_t net, const float *X, int64_t n, int64_t ldx, const float *t, float lr, float *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid hipMalloc): fr_mlp_train_step with the same arguments,
+ * kernels and results, bit for bit, but its per-sample activations, deltas and gradient partial
+ * sums live in a fixed scratch array (14.2 MiB) that the library holds on each GPU it runs on
+ * until the process ends, instead of buffers the network grows with hipMalloc. Nothing is
+ * allocated or freed. n must be 1..FR_MLP_NOALLOC_MAX_N (FR_ERR_ARG beyond). Every call on one GPU
+ * shares that GPU's array and overwrites it: calls that overlap in time on one GPU (other
+ * streams, threads or networks) race and must be ordered by the caller. Enqueued on the
+ * network's stream. */
+#define FR_MLP_NOALLOC_MAX_N 8192
+int fr_mlp_train_step_noalloc(fr_mlp_t net, const float *X, int64_t n, int64_t ldx, const float *t, float lr,
+                              float *loss);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *fr_last_error(void);
 

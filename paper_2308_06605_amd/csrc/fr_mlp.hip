@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -393,9 +394,29 @@ NetArgs args_of(const Net &n) {
   return a;
 }
 
+// Per-sample training buffers (activations, deltas, loss terms) and the per-split partial sums of
+// the gradient: the network's own growing buffers, or a share of the fixed scratch array.
+struct TrainBufs {
+  float *xh = nullptr, *h1 = nullptr, *h2 = nullptr, *d1 = nullptr, *d2 = nullptr, *dz = nullptr, *sq = nullptr;
+  float *part = nullptr;
+};
+
+TrainBufs net_bufs(const Net &n) {
+  TrainBufs b;
+  b.xh = n.xh;
+  b.h1 = n.h1;
+  b.h2 = n.h2;
+  b.d1 = n.d1;
+  b.d2 = n.d2;
+  b.dz = n.dz;
+  b.sq = n.sq;
+  b.part = n.part;
+  return b;
+}
+
 template <bool TRAIN>
 int launch_mlp(const Net &net, hipStream_t st, const float *X, int64_t n, int64_t ldx, float *y, double *nu,
-               double nu_scale, const float *tgt) {
+               double nu_scale, const float *tgt, const TrainBufs &tb = TrainBufs()) {
   const NetArgs a = args_of(net);
   const unsigned blocks = (unsigned)((n + 63) / 64);
   const float inv_n = 1.f / (float)n;
@@ -403,7 +424,7 @@ int launch_mlp(const Net &net, hipStream_t st, const float *X, int64_t n, int64_
 #define CASE(K)                                                                                                  \
   case K:                                                                                                        \
     hipLaunchKernelGGL((k_mlp<K, TRAIN>), dim3(blocks), dim3(256), 0, st, a, X, n, ldx, y, nu, nu_scale, tgt,   \
-                       inv_n, net.xh, net.h1, net.h2, net.d1, net.d2, net.dz, net.sq);                            \
+                       inv_n, tb.xh, tb.h1, tb.h2, tb.d1, tb.d2, tb.dz, tb.sq);                                   \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -436,21 +457,25 @@ int ensure_scratch(Net &net, int64_t n) {
   return FR_OK;
 }
 
-// forward + backward + gradient reduction; then the Adam kernel (update or export only)
+// forward + backward + gradient reduction; then the Adam kernel (update or export only). fixed:
+// training buffers to use instead of the network's own (which are grown here otherwise).
 int grad_pass(fr_mlp_t m, const float *X, int64_t n, int64_t ldx, const float *t, bool update, float lr,
-              float *loss_dev) {
+              float *loss_dev, const TrainBufs *fixed = nullptr) {
   Net &net = m->net;
   if (!X || !t || n <= 0 || ldx < net.F) return fr_fail(FR_ERR_ARG, "bad X / t / n / ldx");
-  int rc = ensure_scratch(net, n);
-  if (rc) return rc;
-  rc = launch_mlp<true>(net, m->stream, X, n, ldx, nullptr, nullptr, 0.0, t);
+  if (!fixed) {
+    int rc = ensure_scratch(net, n);
+    if (rc) return rc;
+  }
+  const TrainBufs tb = fixed ? *fixed : net_bufs(net);
+  int rc = launch_mlp<true>(net, m->stream, X, n, ldx, nullptr, nullptr, 0.0, t, tb);
   if (rc) return rc;
   const int KT = net.FP / 16;
   const int64_t splits = (n + kSplit - 1) / kSplit;
   const int jobs = 4 * KT + 16 + 4;
   hipLaunchKernelGGL(k_mlp_wgrad, dim3(jobs, (unsigned)splits), dim3(64), 0, m->stream, net.F, net.FP, KT, n,
-                     net.xh, net.h1, net.h2, net.d1, net.d2, net.dz, net.sq, net.np, net.oW1, net.ob1, net.oW2,
-                     net.ob2, net.ow3, net.ob3, 1.f / (float)n, net.part);
+                     tb.xh, tb.h1, tb.h2, tb.d1, tb.d2, tb.dz, tb.sq, net.np, net.oW1, net.ob1, net.oW2,
+                     net.ob2, net.ow3, net.ob3, 1.f / (float)n, tb.part);
   MCHK(hipGetLastError());
   float c1 = 1.f, c2 = 1.f;
   if (update) {
@@ -458,7 +483,7 @@ int grad_pass(fr_mlp_t m, const float *X, int64_t n, int64_t ldx, const float *t
     c1 = (float)(1.0 / (1.0 - std::pow(0.9, net.step)));
     c2 = (float)(1.0 / (1.0 - std::pow(0.999, net.step)));
   }
-  hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((net.np + 1 + 255) / 256)), dim3(256), 0, m->stream, net.part,
+  hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((net.np + 1 + 255) / 256)), dim3(256), 0, m->stream, tb.part,
                      (int)splits, net.np, update ? nullptr : net.grad, loss_dev, update ? 1 : 0, lr, c1, c2,
                      net.theta, net.am, net.av, net.F, net.FP, net.oW1, net.oW2, net.ow3, net.W1b, net.W2b,
                      net.W2Tb, net.w3r);
@@ -485,6 +510,57 @@ void free_net(Net &n) {
                   (void *)n.d1, (void *)n.d2, (void *)n.dz, (void *)n.sq, (void *)n.part, (void *)n.grad,
                   (void *)n.dloss})
     if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Training without allocation (fr_mlp_train_step_noalloc): the training buffers of one call live
+// in `scratch`, a fixed array each GPU holds for the life of the process, sized for
+// kNoAllocMaxN samples at the largest input count. Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and is kept here.
+// ------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNoAllocMaxN = FR_MLP_NOALLOC_MAX_N;
+constexpr int64_t kMaxParams = (int64_t)H * kMaxIn + H + H * H + H + H + 1;
+constexpr int64_t kAlignFloats = 64;  // 256 bytes between the sub-buffers
+constexpr int64_t align_floats(int64_t x) { return (x + kAlignFloats - 1) / kAlignFloats * kAlignFloats; }
+constexpr int64_t scratch_floats(int64_t n, int64_t fp, int64_t np) {
+  return align_floats(n * fp) + 4 * align_floats(n * H) + 2 * align_floats(n) +
+         align_floats(((n + kSplit - 1) / kSplit) * (np + 1));
+}
+constexpr int64_t kScratchFloats = scratch_floats(kNoAllocMaxN, kMaxIn, kMaxParams);  // 14.2 MiB
+
+}  // namespace
+
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev (looked up once per device, that device made
+// current for the lookup).
+int scratch_address(int dev, float **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fr_fail(FR_ERR_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    int cur = -1;
+    MCHK(hipGetDevice(&cur));
+    if (cur != dev) MCHK(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fr_fail(FR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = (float *)p;
+  }
+  *out = g_scratch_addr[dev];
+  return FR_OK;
 }
 
 }  // namespace
@@ -637,6 +713,37 @@ int fr_mlp_train_step(fr_mlp_t m, const float *X, int64_t n, int64_t ldx, const 
   if (!valid(m)) return fr_fail(FR_ERR_ARG, "invalid network handle");
   if (!(lr > 0.f)) return fr_fail(FR_ERR_ARG, "lr must be > 0");
   return grad_pass(m, X, n, ldx, t, true, lr, loss);
+}
+
+int fr_mlp_train_step_noalloc(fr_mlp_t m, const float *X, int64_t n, int64_t ldx, const float *t, float lr,
+                              float *loss) {
+  if (!valid(m)) return fr_fail(FR_ERR_ARG, "invalid network handle");
+  if (!(lr > 0.f)) return fr_fail(FR_ERR_ARG, "lr must be > 0");
+  if (n <= 0 || n > kNoAllocMaxN)
+    return fr_fail(FR_ERR_ARG, "n must be in 1.." + std::to_string(kNoAllocMaxN) + " for the no-allocation step");
+  const Net &net = m->net;
+  if (scratch_floats(n, net.FP, net.np) > kScratchFloats) return fr_fail(FR_ERR_ARG, "batch exceeds the scratch array");
+  float *base = nullptr;
+  int rc = scratch_address(m->device, &base);
+  if (rc) return rc;
+  // every entry of these buffers that a kernel reads is first written by this call's kernels
+  // (activations and deltas for samples < n, every partial sum of every split)
+  TrainBufs tb;
+  float *q = base;
+  auto take = [&](int64_t nf) {
+    float *r = q;
+    q += align_floats(nf);
+    return r;
+  };
+  tb.xh = take(n * net.FP);
+  tb.h1 = take(n * H);
+  tb.h2 = take(n * H);
+  tb.d1 = take(n * H);
+  tb.d2 = take(n * H);
+  tb.dz = take(n);
+  tb.sq = take(n);
+  tb.part = take(((n + kSplit - 1) / kSplit) * (net.np + 1));
+  return grad_pass(m, X, n, ldx, t, true, lr, loss, &tb);
 }
 
 }  // extern "C"

@@ -102,6 +102,7 @@ def load():
     L.fr_mlp_forward.argtypes = [P, P, i64, i64, P]
     L.fr_mlp_loss_grad.argtypes = [P, P, i64, i64, P, P, ctypes.POINTER(f64)]
     L.fr_mlp_train_step.argtypes = [P, P, i64, i64, P, ctypes.c_float, P]
+    L.fr_mlp_train_step_noalloc.argtypes = [P, P, i64, i64, P, ctypes.c_float, P]
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
                  "fr_mesh_geometry_host", "fr_basis_host", "fr_rk_coefficients", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
@@ -110,7 +111,7 @@ def load():
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
                  "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
                  "fr_mlp_get_params", "fr_mlp_get_bf16", "fr_mlp_forward", "fr_mlp_loss_grad",
-                 "fr_mlp_train_step"):
+                 "fr_mlp_train_step", "fr_mlp_train_step_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -376,6 +377,7 @@ class FRMesh:
 
 
 H = 64
+MLP_NOALLOC_MAX_N = 8192  # FR_MLP_NOALLOC_MAX_N of include/fr.h
 
 
 def mlp_n_params(n_in: int) -> int:
@@ -474,6 +476,15 @@ class MLP:
         tp = self._t(t, n)
         lp = self._t(loss_out, 1, "loss_out") if loss_out is not None else None
         _check(load().fr_mlp_train_step(self.h, xp, n, ld, tp, float(lr), lp))
+
+    def train_step_noalloc(self, X, t, lr: float, loss_out=None):
+        """One Adam step like train_step, through fr_mlp_train_step_noalloc: its training buffers
+        are the library's fixed per-GPU scratch array (nothing is allocated); n must be at most
+        MLP_NOALLOC_MAX_N. Calls on one GPU share that array, so they must not overlap in time."""
+        xp, n, ld = self._x(X)
+        tp = self._t(t, n)
+        lp = self._t(loss_out, 1, "loss_out") if loss_out is not None else None
+        _check(load().fr_mlp_train_step_noalloc(self.h, xp, n, ld, tp, float(lr), lp))
 
 
 class Batch:
