@@ -261,6 +261,73 @@ int fr_batch_set_stream(fr_batch_t b, void *hip_stream);
 int fr_batch_destroy(fr_batch_t b);
 
 /* ==========================================================================================
+ * Partition groups: a mesh split into parts that exchange their shared faces, the one-GPU form
+ * of the paper's multi-process run (section "Pre-processor Parallelization": each process holds
+ * a part, faces shared with other parts are matched by their vertex ids; section "Three-level
+ * Parallelization Design"). Each part is a mesh handle with its own elements (the part's elements
+ * of the whole mesh in increasing order; state layout [n_local][5][N_s]) whose face buffer also
+ * holds ghost slots for the other parts' sides of the shared faces. With BR2 a stage needs one
+ * exchange, between the pre-pass (the face values and broken gradient) and the face kernel: each
+ * part packs its side of the faces it shares with part q into one contiguous message
+ * (fr_halo_pack), which part q scatters into its ghost slots (fr_halo_unpack); in a
+ * multi-process run the message would travel between the two (RCCL send/receive over xGMI).
+ * Both parts of a shared face compute its common flux from the same data with the whole mesh's
+ * normal and orientation, so the group's results equal the unsplit mesh's bit for bit.
+ * ========================================================================================== */
+typedef struct fr_part_s *fr_part_t;
+
+/* Split the mesh of desc by part[n_elem] (values 0..n_part-1, every part non-empty; 1 <= n_part
+ * <= 1024) and create every part on the current device, enqueued on hip_stream, with one device
+ * message buffer per ordered pair of parts that share faces. The whole mesh's setup (face
+ * pairing, metrics, normals) is done once and split. Needs the BR2 viscous flux
+ * (FR_ERR_UNSUPPORTED with FR_LDG, which would need a second exchange per stage). Errors as
+ * fr_mesh_create, and FR_ERR_ARG for a bad part map. */
+int fr_part_create(const fr_mesh_desc *desc, const int32_t *part, int32_t n_part, void *hip_stream,
+                   fr_part_t *out);
+int fr_part_destroy(fr_part_t g);
+
+/* Host-only: the split of part q without a GPU, for inspection: its element count, ghost face
+ * slots, and per other part r the faces it sends to r and receives from r (n_send, n_recv
+ * [n_part], may be NULL). */
+int fr_part_host(const fr_mesh_desc *desc, const int32_t *part, int32_t n_part, int32_t q, int64_t *n_local,
+                 int64_t *n_ghost, int64_t *n_send, int64_t *n_recv);
+
+/* The handle of part q, owned by the group: fr_set_state, fr_get_state, fr_sol_coords,
+ * fr_set_tiles, fr_set_fusion, fr_set_body_force and fr_mesh_info act on it as on any mesh;
+ * fr_residual, fr_rk_step, fr_kinetic_energy, fr_autotune, fr_profile_stages, the closure and
+ * batches refuse it (FR_ERR_UNSUPPORTED), and fr_mesh_destroy refuses it (FR_ERR_ARG). */
+int fr_part_get_mesh(fr_part_t g, int32_t q, fr_mesh_t *m);
+
+/* Part q's element count and (global_ids may be NULL) its elements' indices in the whole mesh,
+ * host array [n_local], increasing. */
+int fr_part_elements(fr_part_t g, int32_t q, int64_t *n_local, int64_t *global_ids);
+
+/* Enqueue every part's work on hip_stream from now on. */
+int fr_part_set_stream(fr_part_t g, void *hip_stream);
+
+/* The message part m sends to part q: its number of shared faces and its size in bytes (per face
+ * the 20 face values of N_fp points in the handle's face precision; in the FP32 form the 20
+ * floats of every face, padded to 256 bytes, then the 3 momentum doubles of N_fp points). */
+int fr_halo_size(fr_mesh_t m, int32_t q, int64_t *n_faces, int64_t *bytes);
+
+/* Gather part m's side of the faces it shares with part q from its face buffer into the device
+ * buffer send (fr_halo_size bytes), and scatter the message part q packed for m into m's ghost
+ * slots. Both are enqueued on m's stream; the faces are in the whole mesh's face order on both
+ * sides. Errors: FR_ERR_ARG (not a part, q out of range, NULL buffer with faces to move). */
+int fr_halo_pack(fr_mesh_t m, int32_t q, void *send);
+int fr_halo_unpack(fr_mesh_t m, int32_t q, const void *recv);
+
+/* Every part's residual R[q] ([n_local(q)][5][N_s]; all device or all host pointers): the
+ * pre-pass of every part, the exchange, then every part's face and volume kernels. */
+int fr_part_residual(fr_part_t g, double *const *R, int on_device);
+
+/* n_steps RK steps of the whole group in lockstep: per stage, every part's pre-pass (or the
+ * previous stage's fused one), the exchange, then every part's face and volume kernels.
+ * Enqueued; returns without waiting. The closure is not exchanged between parts
+ * (FR_ERR_UNSUPPORTED if a part has one). */
+int fr_part_rk_step(fr_part_t g, double dt, int scheme, int n_steps);
+
+/* ==========================================================================================
  * Learned eddy-viscosity closure (an LES sub-grid scale model; section "ZFR Framework" lists
  * such models among the solver's physical models without specifying one).
  *

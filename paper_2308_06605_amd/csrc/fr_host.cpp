@@ -630,4 +630,77 @@ std::string build_host_mesh(int p, int q, int64_t E, const int64_t *ev, const do
   return "";
 }
 
+std::string build_partition(const HostMesh &G, const int32_t *part, int n_part, int which, HostPart &P) {
+  const int64_t E = G.E;
+  const int n = G.p + 1, Ns = n * n * n, Nfp = n * n;
+  std::vector<int64_t> loc((size_t)E, -1);
+  P.elems.clear();
+  for (int64_t e = 0; e < E; ++e) {
+    if (part[e] < 0 || part[e] >= n_part) return "element " + std::to_string(e) + " has a part outside 0..n_part-1";
+    if (part[e] == which) {
+      loc[e] = (int64_t)P.elems.size();
+      P.elems.push_back(e);
+    }
+  }
+  const int64_t El = (int64_t)P.elems.size();
+  if (El == 0) return "part " + std::to_string(which) + " has no elements";
+  HostMesh &H = P.H;
+  H.p = G.p;
+  H.q = G.q;
+  H.E = El;
+  H.n_wall = 0;
+  H.ops = G.ops;
+  H.geo.resize((size_t)El * 10 * Ns);
+  H.xyz.resize((size_t)El * 3 * Ns);
+  H.conn.assign((size_t)El * 6, FaceConn{-1, 0});
+  for (int64_t l = 0; l < El; ++l) {
+    const int64_t e = P.elems[l];
+    std::copy(&G.geo[(size_t)e * 10 * Ns], &G.geo[(size_t)(e + 1) * 10 * Ns], &H.geo[(size_t)l * 10 * Ns]);
+    std::copy(&G.xyz[(size_t)e * 3 * Ns], &G.xyz[(size_t)(e + 1) * 3 * Ns], &H.xyz[(size_t)l * 3 * Ns]);
+  }
+  H.ftab.clear();
+  H.fgeo.clear();
+  H.fref.assign((size_t)El * 6, FaceRef{-1, 0});
+  P.send.assign(n_part, {});
+  P.recv.assign(n_part, {});
+  P.n_ghost = 0;
+  // every face with a side in this part, in the whole mesh's face order
+  for (size_t fid = 0; fid < G.ftab.size(); ++fid) {
+    const FaceRec r = G.ftab[fid];
+    const int fL = r.code & 7, fR = (r.code >> 3) & 7;
+    const bool wall = (r.code & kFaceWall) != 0;
+    const bool inL = loc[r.eL] >= 0;
+    const bool inR = !wall && loc[r.eR] >= 0;
+    if (!inL && !inR) continue;
+    FaceRec lr = r;
+    const int32_t lid = (int32_t)H.ftab.size();
+    if (inL) {
+      lr.eL = (int32_t)loc[r.eL];
+      H.fref[(size_t)lr.eL * 6 + fL] = FaceRef{lid, G.fref[(size_t)r.eL * 6 + fL].code};
+    } else {  // the owner side is another part's: a ghost slot
+      const int64_t g = P.n_ghost++;
+      lr.eL = (int32_t)(El + g / 6);
+      lr.code = (lr.code & ~7) | (int32_t)(g % 6);
+      P.recv[part[r.eL]].push_back((int32_t)g);
+      P.send[part[r.eL]].push_back((int32_t)(loc[r.eR] * 6 + fR));
+    }
+    if (wall) {
+      ++H.n_wall;
+    } else if (inR) {
+      lr.eR = (int32_t)loc[r.eR];
+      H.fref[(size_t)lr.eR * 6 + fR] = FaceRef{lid, G.fref[(size_t)r.eR * 6 + fR].code};
+    } else {
+      const int64_t g = P.n_ghost++;
+      lr.eR = (int32_t)(El + g / 6);
+      lr.code = (lr.code & ~(7 << 3)) | (int32_t)((g % 6) << 3);
+      P.recv[part[r.eR]].push_back((int32_t)g);
+      P.send[part[r.eR]].push_back((int32_t)(loc[r.eL] * 6 + fL));
+    }
+    H.ftab.push_back(lr);
+    H.fgeo.insert(H.fgeo.end(), &G.fgeo[fid * 4 * Nfp], &G.fgeo[(fid + 1) * 4 * Nfp]);
+  }
+  if (El * 6 + P.n_ghost > (int64_t)INT32_MAX) return "too many face slots in part " + std::to_string(which);
+  return "";
+}
+
 }  // namespace frk

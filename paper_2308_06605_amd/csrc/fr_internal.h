@@ -1,10 +1,13 @@
-// fr_internal.h -- library-private declarations shared by the host setup (fr_host.cpp) and the
-// HIP kernels (fr_kernels.hip). Not part of the C ABI.
+// fr_internal.h -- library-private declarations shared by the host setup (fr_host.cpp), the HIP
+// kernels and entry points (fr_kernels.hip, fr_kernels32.hip, fr_mlp.hip) and the partition
+// groups (fr_partition.hip). Not part of the C ABI.
 #pragma once
 
 #include <cstdint>
 #include <string>
 #include <vector>
+
+#include "fr.h"
 
 struct fr_mlp_s;
 
@@ -95,7 +98,8 @@ struct StageArgs {
   int32_t force;
   int32_t pre_done;  // host: the face buffer already holds this stage's pre-pass
   int32_t pre_next;  // the volume kernel also writes the next stage's pre-pass
-  int32_t pad;
+  int32_t pre_only;  // host: launch the stage's pre-pass and nothing else (partition groups
+                     // exchange the face data between the pre-pass and the face kernel)
 };
 
 // Device buffers of one mesh (FP64 or FP32 operator path; the state is always FP64).
@@ -145,13 +149,16 @@ struct DeviceMesh {
   fr_mlp_s *model = nullptr;
   double nu_scale = 0.0, prandtl_t = 0.9;
   SgsOps sgs_ops;
+  int64_t n_ghost = 0;    // face slots after the 6E local ones in face / face32 / facem: the
+                          // other parts' faces of a partition group, filled by the halo unpack
   int *flag = nullptr;    // non-finite flag
   bool check_finite = false;
   void *stream = nullptr;
   int64_t bytes = 0;
 };
 
-// Host-side arrays of a mesh, built once by build_host_mesh (fr_host.cpp).
+// Host-side arrays of a mesh, built once by build_host_mesh (fr_host.cpp); for a part of a
+// partition group, by build_partition from the whole mesh's.
 struct HostMesh {
   int p = 0, q = 1;
   int64_t E = 0;
@@ -187,4 +194,62 @@ int mlp_forward_nu(fr_mlp_s *m, const float *X, int64_t n, int64_t ldx, double *
 std::string build_host_mesh(int p, int q, int64_t E, const int64_t *elem_vert, const double *elem_nodes,
                             const int32_t *bc_tag, double br2_eta, HostMesh &H);
 
+// One part of a mesh split into parts by an element -> part map (the paper's pre-processor splits
+// the mesh across processes; section "Pre-processor Parallelization"). Its elements are the
+// part's, in increasing global order. Its face list is every face of the whole mesh (in the whole
+// mesh's owner order) with at least one side in the part, with the whole mesh's normals, BR2
+// factors and orientation codes; a side in another part is a ghost face slot 6 E_loc + g of the
+// face buffer, written as element E_loc + g / 6 and local face g % 6 of the face record. send[q]
+// lists the face-buffer slots (6 e + f) of the part's own faces whose other side is in part q,
+// recv[q] the ghost slots g those faces of part q fill; both in the whole mesh's face order, so
+// part a's send[b] and part b's recv[a] name the same faces in the same order.
+struct HostPart {
+  std::vector<int64_t> elems;  // local -> global element index
+  HostMesh H;                  // the part's arrays (E = elems.size())
+  int64_t n_ghost = 0;
+  std::vector<std::vector<int32_t>> send, recv;  // [n_part]
+};
+
+std::string build_partition(const HostMesh &G, const int32_t *part, int n_part, int which, HostPart &P);
+
+// Stage plumbing shared by the single-mesh entry points (fr_kernels.hip) and the partition
+// groups (fr_partition.hip).
+int n_stages(int scheme);  // 4, 5 or 10; 0 for an unknown scheme
+// The register update of stage s of `scheme` with step dt (st.mode, coefficients) and the state,
+// output and register arrays that stage reads and writes on the handle's buffers.
+void stage_setup(DeviceMesh &dm, int scheme, int s, double dt, StageArgs &st, const double **X, double **out0,
+                 double **reg1, double **reg2);
+int ensure_registers(DeviceMesh &dm, int scheme);
+// Enqueue one stage (or its pre-pass alone, st.pre_only) with the handle's source term; 0 or an
+// FR_ERR_* code with the message set.
+int enqueue_stage(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2);
+
+}  // namespace frk
+
+// The opaque mesh handle of the C ABI.
+struct fr_part_s;
+struct fr_mesh_s {
+  uint64_t magic;
+  frk::DeviceMesh dm;
+  std::vector<double> xyz;
+  int device;
+  // a part of a partition group (fr_part_create): the group owns it; the device lists of face
+  // slots exchanged with each other part (send: own faces packed for part q; recv: ghost slots
+  // unpacked from part q) and their lengths in faces
+  fr_part_s *group = nullptr;
+  std::vector<int32_t *> send_slots, recv_slots;
+  std::vector<int64_t> n_send, n_recv;
+};
+
+namespace frk {
+constexpr uint64_t kMeshMagic = 0x46524d4553484d31ull;  // "FRMESHM1"
+inline bool valid_mesh(const fr_mesh_s *m) { return m != nullptr && m->magic == kMeshMagic; }
+// The argument checks of fr_mesh_create, and the host setup with its wall checks; 0 or an
+// FR_ERR_* code with the message set.
+int validate_desc(const fr_mesh_desc *d);
+int host_mesh_of(const fr_mesh_desc *d, HostMesh &H);
+// Device buffers of a mesh from its host arrays (n_ghost extra face slots); *out on success.
+int create_device_mesh(const fr_mesh_desc *d, HostMesh &H, int64_t n_ghost, void *stream, fr_mesh_s **out);
+// Free a handle's device memory and the handle (waits for its stream).
+int destroy_device_mesh(fr_mesh_s *m);
 }  // namespace frk

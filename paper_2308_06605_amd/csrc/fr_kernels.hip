@@ -889,14 +889,6 @@ __global__ void k_nonfinite(const double *__restrict__ R, int64_t n, int *flag) 
 // ==========================================================================================
 // Host side: handle, dispatch, C ABI
 // ==========================================================================================
-struct fr_mesh_s {
-  uint64_t magic;
-  DeviceMesh dm;
-  std::vector<double> xyz;
-  int device;
-};
-
-static constexpr uint64_t kMagic = 0x46524d4553484d31ull;  // "FRMESHM1"
 static thread_local std::string g_err;
 
 static int fail(int code, const std::string &msg) {
@@ -912,7 +904,15 @@ int frk::fr_fail(int code, const std::string &msg) { return fail(code, msg); }
     if (e_ != hipSuccess) return fail(FR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-static bool valid(fr_mesh_t m) { return m != nullptr && m->magic == kMagic; }
+static bool valid(fr_mesh_t m) { return valid_mesh(m); }
+
+// A part of a partition group evaluates its residual only together with the other parts (its
+// ghost faces come from them), through fr_part_residual / fr_part_rk_step.
+static int reject_part(fr_mesh_t m, const char *what) {
+  return m->group ? fail(FR_ERR_UNSUPPORTED, std::string(what) + " on a part of a partition group: use the group's "
+                                             "fr_part_residual / fr_part_rk_step")
+                  : FR_OK;
+}
 
 // ms (optional): accumulates the durations of the three kernels, measured with HIP events.
 template <int P>
@@ -975,6 +975,12 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
   const int64_t blocks = (dm.E + EPBX - 1) / EPBX;
   const int64_t fblocks = (dm.F * C::NFP + FBS - 1) / FBS;
   hipStream_t s = (hipStream_t)dm.stream;
+  if (st.pre_only) {
+    hipLaunchKernelGGL((k_prepass<P, real, VISC && !LDG, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s,
+                       X, (const real *)dm.geo, (real *)dm.face, dm.E, ops);
+    HIPCHK(hipGetLastError());
+    return FR_OK;
+  }
   hipEvent_t ev[4];
   if (ms) {
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
@@ -1091,7 +1097,7 @@ static const double kRk4W[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
 static const double kRk4C[4] = {0.5, 0.5, 1.0, 0.0};
 
 // Allocate the RK registers a scheme needs (before any graph capture: capture cannot allocate).
-static int ensure_registers(DeviceMesh &dm, int scheme) {
+int frk::ensure_registers(DeviceMesh &dm, int scheme) {
   const int64_t M = dm.E * 5 * dm.Ns;
   if (scheme != FR_RK4 && scheme != FR_LSRK45 && scheme != FR_SSPRK104) return fail(FR_ERR_ARG, "unknown scheme");
   if (!dm.R1) {
@@ -1105,92 +1111,68 @@ static int ensure_registers(DeviceMesh &dm, int scheme) {
   return FR_OK;
 }
 
+int frk::n_stages(int scheme) {
+  return scheme == FR_LSRK45 ? 5 : (scheme == FR_RK4 ? 4 : (scheme == FR_SSPRK104 ? 10 : 0));
+}
+
+void frk::stage_setup(DeviceMesh &dm, int scheme, int s, double dt, StageArgs &st, const double **X, double **out0,
+                      double **reg1, double **reg2) {
+  st = StageArgs{};
+  st.dt = dt;
+  *X = dm.U;
+  *out0 = dm.U;
+  *reg1 = dm.R1;
+  *reg2 = nullptr;
+  if (scheme == FR_LSRK45) {
+    st.mode = kModeLSRK;
+    st.first = s == 0;
+    st.a = kLsA[s];
+    st.b = kLsB[s];
+  } else if (scheme == FR_RK4) {
+    st.mode = kModeRK4;
+    st.first = s == 0;
+    st.last = s == 3;
+    st.w = kRk4W[s];
+    st.cdt = kRk4C[s] * dt;
+    *X = s == 0 ? dm.U : dm.R2;
+    *reg2 = dm.R2;
+  } else {
+    st.mode = kModeSSP;
+    st.stage = s;
+  }
+}
+
+int frk::enqueue_stage(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2) {
+  return launch_stage(dm, X, st, out0, reg1, reg2, nullptr);
+}
+
 static int run_steps(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms_acc) {
   DeviceMesh &dm = m->dm;
-  const int64_t M = dm.E * 5 * dm.Ns;
+  const int ns = n_stages(scheme);
+  if (ns == 0) return fail(FR_ERR_ARG, "unknown scheme");
   if (n_steps > 0) {
     int rc = ensure_registers(dm, scheme);
     if (rc) return rc;
   }
-  (void)M;
   // With fusion on every stage but the run's first finds its pre-pass already done by the
   // previous stage's volume kernel, and every stage but the run's last does the next one's.
-  const int n_stages = scheme == FR_LSRK45 ? 5 : (scheme == FR_RK4 ? 4 : 10);
-  auto chain = [&](StageArgs &st, int step, int s) {
-    st.pre_done = dm.fuse && !(step == 0 && s == 0);
-    st.pre_next = dm.fuse && !(step == n_steps - 1 && s == n_stages - 1);
-  };
   for (int step = 0; step < n_steps; ++step) {
-    if (scheme == FR_LSRK45) {
-      if (!dm.R1) {
-        HIPCHK(hipMalloc(&dm.R1, M * sizeof(double)));
-        dm.bytes += M * sizeof(double);
-      }
-      for (int s = 0; s < 5; ++s) {
-        StageArgs st{};
-        st.mode = kModeLSRK;
-        st.first = s == 0;
-        st.a = kLsA[s];
-        st.b = kLsB[s];
-        st.dt = dt;
-        chain(st, step, s);
-        int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, ms_acc);
-        if (rc) return rc;
-        if (ms_acc) ms_acc[3] += 1;
-      }
-    } else if (scheme == FR_RK4) {
-      if (!dm.R1) {
-        HIPCHK(hipMalloc(&dm.R1, M * sizeof(double)));
-        dm.bytes += M * sizeof(double);
-      }
-      if (!dm.R2) {
-        HIPCHK(hipMalloc(&dm.R2, M * sizeof(double)));
-        dm.bytes += M * sizeof(double);
-      }
-      const double *w = kRk4W, *c = kRk4C;
-      for (int s = 0; s < 4; ++s) {
-        StageArgs st{};
-        st.mode = kModeRK4;
-        st.first = s == 0;
-        st.last = s == 3;
-        st.w = w[s];
-        st.cdt = c[s] * dt;
-        st.dt = dt;
-        chain(st, step, s);
-        const double *X = s == 0 ? dm.U : dm.R2;
-        int rc = launch_stage(dm, X, st, dm.U, dm.R1, dm.R2, ms_acc);
-        if (rc) return rc;
-        if (ms_acc) ms_acc[3] += 1;
-      }
-    } else if (scheme == FR_SSPRK104) {
-      if (!dm.R1) {
-        HIPCHK(hipMalloc(&dm.R1, M * sizeof(double)));
-        dm.bytes += M * sizeof(double);
-      }
-      for (int s = 0; s < 10; ++s) {
-        StageArgs st{};
-        st.mode = kModeSSP;
-        st.stage = s;
-        st.dt = dt;
-        chain(st, step, s);
-        int rc = launch_stage(dm, dm.U, st, dm.U, dm.R1, nullptr, ms_acc);
-        if (rc) return rc;
-        if (ms_acc) ms_acc[3] += 1;
-      }
-    } else {
-      return fail(FR_ERR_ARG, "unknown scheme");
+    for (int s = 0; s < ns; ++s) {
+      StageArgs st;
+      const double *X;
+      double *o, *r1, *r2;
+      stage_setup(dm, scheme, s, dt, st, &X, &o, &r1, &r2);
+      st.pre_done = dm.fuse && !(step == 0 && s == 0);
+      st.pre_next = dm.fuse && !(step == n_steps - 1 && s == ns - 1);
+      int rc = launch_stage(dm, X, st, o, r1, r2, ms_acc);
+      if (rc) return rc;
+      if (ms_acc) ms_acc[3] += 1;
     }
   }
   return FR_OK;
 }
 
-extern "C" {
-
-const char *fr_last_error(void) { return g_err.c_str(); }
-
-int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
-  if (!out) return fail(FR_ERR_ARG, "out is NULL");
-  *out = nullptr;
+int frk::validate_desc(const fr_mesh_desc *d) {
   if (!d) return fail(FR_ERR_ARG, "desc is NULL");
   if (d->p < 0 || d->p > kMaxP) return fail(FR_ERR_ARG, "p must be in 0..7");
   if (d->q < 1 || d->q > (d->p > 1 ? d->p : 1)) return fail(FR_ERR_ARG, "q must be in 1..max(p,1)");
@@ -1207,7 +1189,10 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   if (d->viscous == FR_LDG && !(d->ldg_tau >= 0.0 && std::isfinite(d->ldg_tau)))
     return fail(FR_ERR_ARG, "ldg_tau must be finite and >= 0");
 
-  HostMesh H;
+  return FR_OK;
+}
+
+int frk::host_mesh_of(const fr_mesh_desc *d, HostMesh &H) {
   std::string err = build_host_mesh(d->p, d->q, d->n_elem, d->elem_vert, d->elem_nodes, d->bc_tag, d->br2_eta, H);
   if (!err.empty()) return fail(FR_ERR_MESH, err);
   if (H.n_wall > 0) {
@@ -1215,14 +1200,18 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
     if (!(d->wall_T > 0.0) || !std::isfinite(d->wall_T)) return fail(FR_ERR_ARG, "wall_T must be finite and > 0");
   }
 
+  return FR_OK;
+}
+
+int frk::create_device_mesh(const fr_mesh_desc *d, HostMesh &H, int64_t n_ghost, void *hip_stream, fr_mesh_s **out) {
   fr_mesh_s *m = new fr_mesh_s();
-  m->magic = kMagic;
+  m->magic = kMeshMagic;
   DeviceMesh &dm = m->dm;
   dm.p = d->p;
   dm.n = d->p + 1;
   dm.Ns = dm.n * dm.n * dm.n;
   dm.Nfp = dm.n * dm.n;
-  dm.E = d->n_elem;
+  dm.E = H.E;
   dm.prec = d->prec;
   dm.flux = d->flux;
   dm.viscous = d->mu > 0.0;
@@ -1257,13 +1246,13 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
   if (!rc) rc = alloc((void **)&dm.fref, H.fref.size() * sizeof(FaceRef));
   std::vector<float> geo32;
   if (dm.prec == FR_FP64) {
-    if (!rc) rc = alloc(&dm.face, (size_t)dm.E * 6 * 20 * dm.Nfp * sizeof(double));
+    if (!rc) rc = alloc(&dm.face, (size_t)(dm.E * 6 + n_ghost) * 20 * dm.Nfp * sizeof(double));
     if (!rc) rc = alloc(&dm.fout, (size_t)dm.F * 10 * dm.Nfp * sizeof(double));
   } else {
     geo32.assign(H.geo.begin(), H.geo.end());
     if (!rc) rc = alloc(&dm.geo32, geo32.size() * sizeof(float));
-    if (!rc) rc = alloc(&dm.face32, (size_t)dm.E * 6 * 20 * dm.Nfp * sizeof(float));
-    if (!rc) rc = alloc(&dm.facem, (size_t)dm.E * 6 * 3 * dm.Nfp * sizeof(double));
+    if (!rc) rc = alloc(&dm.face32, (size_t)(dm.E * 6 + n_ghost) * 20 * dm.Nfp * sizeof(float));
+    if (!rc) rc = alloc(&dm.facem, (size_t)(dm.E * 6 + n_ghost) * 3 * dm.Nfp * sizeof(double));
     if (!rc) rc = alloc(&dm.fout32, (size_t)dm.F * 9 * dm.Nfp * sizeof(float));
     if (!rc) rc = alloc(&dm.foutm, (size_t)dm.F * dm.Nfp * sizeof(double));
   }
@@ -1287,6 +1276,27 @@ int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
     return fail(FR_ERR_HIP, "upload of mesh data failed");
   }
   dm.check_finite = d->check_finite != 0;
+  dm.n_ghost = n_ghost;
+  *out = m;
+  return FR_OK;
+}
+
+
+extern "C" {
+
+const char *fr_last_error(void) { return g_err.c_str(); }
+
+int fr_mesh_create(const fr_mesh_desc *d, void *hip_stream, fr_mesh_t *out) {
+  if (!out) return fail(FR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  HostMesh H;
+  rc = host_mesh_of(d, H);
+  if (rc) return rc;
+  fr_mesh_s *m = nullptr;
+  rc = create_device_mesh(d, H, 0, hip_stream, &m);
+  if (rc) return rc;
   *out = m;
   return FR_OK;
 }
@@ -1347,6 +1357,13 @@ int fr_rk_coefficients(int scheme, double *a, double *b, int32_t *n_stages) {
 int fr_mesh_destroy(fr_mesh_t m) {
   if (!m) return FR_OK;
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (m->group) return fail(FR_ERR_ARG, "a part of a partition group is destroyed with its group (fr_part_destroy)");
+  return destroy_device_mesh(m);
+}
+
+}  // extern "C"
+
+int frk::destroy_device_mesh(fr_mesh_s *m) {
   DeviceMesh &dm = m->dm;
   if (dm.stream) (void)hipStreamSynchronize((hipStream_t)dm.stream);
   else (void)hipDeviceSynchronize();
@@ -1355,10 +1372,16 @@ int fr_mesh_destroy(fr_mesh_t m) {
                   dm.feat};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
+  for (int32_t *b : m->send_slots)
+    if (b) (void)hipFree(b);
+  for (int32_t *b : m->recv_slots)
+    if (b) (void)hipFree(b);
   m->magic = 0;
   delete m;
   return FR_OK;
 }
+
+extern "C" {
 
 int fr_set_stream(fr_mesh_t m, void *hip_stream) {
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
@@ -1394,6 +1417,7 @@ int fr_get_state(fr_mesh_t m, double *U, int on_device) {
 
 int fr_residual(fr_mesh_t m, double *R, int on_device) {
   if (!valid(m) || !R) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  if (int rc = reject_part(m, "fr_residual")) return rc;
   DeviceMesh &dm = m->dm;
   const size_t M = (size_t)dm.E * 5 * dm.Ns;
   hipStream_t s = (hipStream_t)dm.stream;
@@ -1429,12 +1453,14 @@ int fr_residual(fr_mesh_t m, double *R, int on_device) {
 
 int fr_rk_step(fr_mesh_t m, double dt, int scheme, int n_steps) {
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (int rc = reject_part(m, "fr_rk_step")) return rc;
   if (n_steps < 0 || !std::isfinite(dt)) return fail(FR_ERR_ARG, "bad dt or n_steps");
   return run_steps(m, dt, scheme, n_steps, nullptr);
 }
 
 int fr_kinetic_energy(fr_mesh_t m, double *out) {
   if (!valid(m) || !out) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  if (int rc = reject_part(m, "fr_kinetic_energy")) return rc;
   DeviceMesh &dm = m->dm;
   const size_t M = (size_t)dm.E * 5 * dm.Ns;
   const int64_t npts = dm.E * dm.Ns;
@@ -1505,6 +1531,7 @@ int fr_get_tiles(fr_mesh_t m, int32_t *epb, int32_t *fbs) {
 
 int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (int rc = reject_part(m, "fr_autotune")) return rc;
   if (n_trials < 1) return fail(FR_ERR_ARG, "n_trials must be >= 1");
   DeviceMesh &dm = m->dm;
   const int64_t M = dm.E * 5 * dm.Ns;
@@ -1608,6 +1635,7 @@ static int ensure_nut(DeviceMesh &dm) {
 
 int fr_set_eddy_viscosity(fr_mesh_t m, const double *nu, int on_device, double prandtl_t) {
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (int rc = reject_part(m, "fr_set_eddy_viscosity")) return rc;
   DeviceMesh &dm = m->dm;
   if (dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "the closure needs prec = FR_FP64");
   if (!nu) {
@@ -1634,6 +1662,7 @@ int fr_set_eddy_viscosity(fr_mesh_t m, const double *nu, int on_device, double p
 
 int fr_set_sgs_model(fr_mesh_t m, fr_mlp_t model, double nu_scale, double prandtl_t) {
   if (!valid(m)) return fail(FR_ERR_ARG, "not a mesh handle");
+  if (int rc = reject_part(m, "fr_set_sgs_model")) return rc;
   DeviceMesh &dm = m->dm;
   if (dm.prec != FR_FP64) return fail(FR_ERR_UNSUPPORTED, "the closure needs prec = FR_FP64");
   if (!model) {
@@ -1698,6 +1727,7 @@ int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int sc
   HIPCHK(hipGetDevice(&dev));
   for (int i = 0; i < n; ++i) {
     if (!valid(meshes[i])) return fail(FR_ERR_ARG, "mesh " + std::to_string(i) + " is not a mesh handle");
+    if (int rc = reject_part(meshes[i], "fr_batch_create")) return rc;
     if (meshes[i]->device != dev) return fail(FR_ERR_ARG, "mesh " + std::to_string(i) + " lives on another device");
     if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(FR_ERR_ARG, "dt must be finite and > 0");
     for (int j = 0; j < i; ++j)
@@ -1799,6 +1829,7 @@ int fr_batch_destroy(fr_batch_t b) {
 
 int fr_profile_stages(fr_mesh_t m, double dt, int scheme, int n_steps, double *ms) {
   if (!valid(m) || !ms) return fail(FR_ERR_ARG, "bad handle or NULL pointer");
+  if (int rc = reject_part(m, "fr_profile_stages")) return rc;
   double acc[kTimeSlots] = {0, 0, 0, 0, 0, 0, 0};
   int rc = run_steps(m, dt, scheme, n_steps, acc);
   if (rc) return rc;

@@ -754,6 +754,12 @@ int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, doub
   const int64_t blocks = (dm.E + EPBX - 1) / EPBX;
   const int64_t fblocks = (dm.F * C::NFP + FBS - 1) / FBS;
   hipStream_t s = (hipStream_t)dm.stream;
+  if (st.pre_only) {
+    hipLaunchKernelGGL((k_prepass32<P, VISC, EPBX>), dim3((unsigned)blocks), dim3(EPBX * C::NS), 0, s, X,
+                       (const float *)dm.geo32, (float *)dm.face32, (double *)dm.facem, dm.E, ops, opsd, ref);
+    HIPCHK32(hipGetLastError());
+    return FR_OK;
+  }
   hipEvent_t ev[4];
   if (ms) {
     for (int i = 0; i < 4; ++i) HIPCHK32(hipEventCreate(&ev[i]));

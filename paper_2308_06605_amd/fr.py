@@ -81,6 +81,18 @@ def load():
     L.fr_autotune.argtypes = [P, i32, P]
     L.fr_set_fusion.argtypes = [P, ctypes.c_int32]
     L.fr_get_fusion.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    L.fr_part_create.argtypes = [ctypes.POINTER(fr_mesh_desc), P, ctypes.c_int32, P, ctypes.POINTER(P)]
+    L.fr_part_destroy.argtypes = [P]
+    L.fr_part_host.argtypes = [ctypes.POINTER(fr_mesh_desc), P, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.POINTER(i64), ctypes.POINTER(i64), P, P]
+    L.fr_part_get_mesh.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
+    L.fr_part_elements.argtypes = [P, ctypes.c_int32, ctypes.POINTER(i64), P]
+    L.fr_part_set_stream.argtypes = [P, P]
+    L.fr_halo_size.argtypes = [P, ctypes.c_int32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.fr_halo_pack.argtypes = [P, ctypes.c_int32, P]
+    L.fr_halo_unpack.argtypes = [P, ctypes.c_int32, P]
+    L.fr_part_residual.argtypes = [P, P, i32]
+    L.fr_part_rk_step.argtypes = [P, f64, i32, i32]
     L.fr_batch_create.argtypes = [P, ctypes.c_int32, P, i32, P, ctypes.POINTER(P)]
     L.fr_batch_step.argtypes = [P, i32]
     L.fr_batch_set_stream.argtypes = [P, P]
@@ -111,7 +123,9 @@ def load():
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
                  "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
                  "fr_mlp_get_params", "fr_mlp_get_bf16", "fr_mlp_forward", "fr_mlp_loss_grad",
-                 "fr_mlp_train_step", "fr_mlp_train_step_noalloc"):
+                 "fr_mlp_train_step", "fr_mlp_train_step_noalloc", "fr_part_create", "fr_part_destroy", "fr_part_host",
+                 "fr_part_get_mesh", "fr_part_elements", "fr_part_set_stream", "fr_halo_size", "fr_halo_pack",
+                 "fr_halo_unpack", "fr_part_residual", "fr_part_rk_step"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -173,6 +187,19 @@ def rk_coefficients(scheme: str):
     return a[:n.value].copy(), b[:n.value].copy()
 
 
+def partition_host(mesh, p: int, part, q: int, bc_tag=None):
+    """Host-only split of part q (fr_part_host): (n_local, n_ghost, n_send[n_part], n_recv[n_part])."""
+    keep = []
+    d = _desc(mesh, p, 0.0, 1.4, 0.72, 6.0, "rusanov", "fp64", False, keep, bc_tag=bc_tag)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    n_part = int(part.max()) + 1
+    nl, ng = ctypes.c_int64(), ctypes.c_int64()
+    ns, nr = np.zeros(n_part, dtype=np.int64), np.zeros(n_part, dtype=np.int64)
+    _check(load().fr_part_host(ctypes.byref(d), part.ctypes.data, n_part, int(q), ctypes.byref(nl), ctypes.byref(ng),
+                               ns.ctypes.data, nr.ctypes.data))
+    return nl.value, ng.value, ns, nr
+
+
 def geometry_host(mesh, p: int, eta: float = 6.0, bc_tag=None):
     """Host-only mesh setup (fr_mesh_geometry_host): geo, fgeo, ftab, conn, xyz as numpy arrays."""
     keep = []
@@ -219,7 +246,23 @@ class FRMesh:
         _check(L.fr_mesh_create(ctypes.byref(d), self._stream, ctypes.byref(h)))
         self.h = h
 
+    @classmethod
+    def _part_view(cls, h, p: int, n_local: int, device: int, stream, group):
+        """A part of a PartitionGroup: the group owns the handle (close() only forgets it)."""
+        self = cls.__new__(cls)
+        self.p = int(p)
+        self.Ns = (self.p + 1) ** 3
+        self.E = int(n_local)
+        self.device = device
+        self._stream = stream
+        self._group = group
+        self.h = h
+        return self
+
     def close(self):
+        if getattr(self, "_group", None) is not None:
+            self.h = None
+            return
         if getattr(self, "h", None) and self.h.value:
             load().fr_mesh_destroy(self.h)
             self.h = None
@@ -485,6 +528,108 @@ class MLP:
         tp = self._t(t, n)
         lp = self._t(loss_out, 1, "loss_out") if loss_out is not None else None
         _check(load().fr_mlp_train_step_noalloc(self.h, xp, n, ld, tp, float(lr), lp))
+
+
+class PartitionGroup:
+    """A mesh split into parts by an element -> part map, advanced together on one GPU with one
+    face exchange per stage (fr_part_*). parts[q] is an FRMesh view of part q (its state is
+    [n_local][5][N_s] over elements[q], the part's global element indices)."""
+
+    def __init__(self, mesh, p: int, part, *, mu: float = 0.0, gamma: float = 1.4, prandtl: float = 0.72,
+                 eta: float = 6.0, flux: str = "rusanov", prec: str = "fp64", stream=None, ref_rho: float = 1.0,
+                 ref_p: float = 0.0, bc_tag=None, wall_T: float = 1.0):
+        import torch
+
+        L = load()
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        E = int(mesh.elem_vert.shape[0])
+        assert part.shape == (E,)
+        self.n_part = int(part.max()) + 1
+        self.p = int(p)
+        self.E = E
+        keep = []
+        d = _desc(mesh, p, mu, gamma, prandtl, eta, flux, prec, False, keep, (ref_rho, ref_p), "br2", 0.1,
+                  bc_tag, wall_T)
+        self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
+        self.device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        _check(L.fr_part_create(ctypes.byref(d), part.ctypes.data, self.n_part, self._stream, ctypes.byref(h)))
+        self.h = h
+        self.parts, self.elements = [], []
+        for q in range(self.n_part):
+            mh, n = ctypes.c_void_p(), ctypes.c_int64()
+            _check(L.fr_part_get_mesh(self.h, q, ctypes.byref(mh)))
+            _check(L.fr_part_elements(self.h, q, ctypes.byref(n), None))
+            ids = np.empty(n.value, dtype=np.int64)
+            _check(L.fr_part_elements(self.h, q, ctypes.byref(n), ids.ctypes.data))
+            self.elements.append(ids)
+            self.parts.append(FRMesh._part_view(mh, p, n.value, self.device, self._stream, self))
+
+    @property
+    def shape(self):
+        return (self.E, 5, (self.p + 1) ** 3)
+
+    def set_state(self, U):
+        """The whole mesh's state [E][5][N_s] (numpy), split over the parts."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == self.shape
+        for m, ids in zip(self.parts, self.elements):
+            m.set_state(U[ids])
+
+    def get_state(self) -> np.ndarray:
+        U = np.empty(self.shape)
+        for m, ids in zip(self.parts, self.elements):
+            U[ids] = m.get_state()
+        return U
+
+    def residual(self) -> np.ndarray:
+        """The whole mesh's residual assembled from the parts' (fr_part_residual)."""
+        Rs = [np.empty(m.shape) for m in self.parts]
+        ptrs = (ctypes.c_void_p * self.n_part)(*[r.ctypes.data for r in Rs])
+        _check(load().fr_part_residual(self.h, ctypes.cast(ptrs, ctypes.c_void_p), 0))
+        R = np.empty(self.shape)
+        for r, ids in zip(Rs, self.elements):
+            R[ids] = r
+        return R
+
+    def rk_step(self, dt: float, scheme: str = "lsrk45", n_steps: int = 1):
+        _check(load().fr_part_rk_step(self.h, float(dt), SCHEME[scheme], int(n_steps)))
+
+    def halo_size(self, q: int, r: int):
+        """(faces, bytes) of the message part q sends to part r."""
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().fr_halo_size(self.parts[q].h, int(r), ctypes.byref(n), ctypes.byref(b)))
+        return n.value, b.value
+
+    def _msg(self, buf, nbytes, what):
+        if not getattr(buf, "is_cuda", False) or not buf.is_contiguous():
+            raise ValueError(f"{what}: expected a contiguous device tensor")
+        if buf.device.index != self.device or buf.numel() * buf.element_size() < nbytes:
+            raise ValueError(f"{what}: needs {nbytes} bytes on device {self.device}")
+        return ctypes.c_void_p(buf.data_ptr())
+
+    def halo_pack(self, q: int, r: int, out):
+        """Part q's side of the faces it shares with part r into the device tensor out."""
+        ptr = self._msg(out, self.halo_size(q, r)[1], "halo_pack")
+        _check(load().fr_halo_pack(self.parts[q].h, int(r), ptr))
+
+    def halo_unpack(self, q: int, r: int, msg):
+        """The message part r packed for part q into q's ghost slots."""
+        ptr = self._msg(msg, self.halo_size(r, q)[1], "halo_unpack")
+        _check(load().fr_halo_unpack(self.parts[q].h, int(r), ptr))
+
+    def close(self):
+        for m in getattr(self, "parts", []):
+            m.h = None
+        if getattr(self, "h", None) and self.h.value:
+            load().fr_part_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
