@@ -149,7 +149,8 @@ int fr_get_tiles(fr_mesh_t m, int32_t *epb, int32_t *fbs);
 
 /* Autotuner: time each tile choice, with and without the fused pre-pass (fr_set_fusion), on
  * this mesh and state: n_trials LSRK stages each from the current state into scratch buffers
- * (HIP events on the handle's stream, after one warm-up stage each), and keep the fastest.
+ * (HIP events on the handle's stream, after one warm-up stage each), and keep the fastest. The
+ * timed stages are later stages of a step (they read and write the RK register).
  * ms (may be NULL) receives 12 mean ms per stage: index fuse * 6 + epb * 3 + fbs, where
  * fuse = 0 times the stand-alone pre-pass + face + volume kernels and fuse = 1 the face kernel
  * + the volume kernel with the next stage's pre-pass. Allocates two state-sized scratch
@@ -174,11 +175,13 @@ int fr_set_body_force(fr_mesh_t m, const double *g);
  * precision, layout [n_elem][5][N_s]. Errors: FR_ERR_ARG, FR_ERR_HIP, FR_ERR_NONFINITE. */
 int fr_residual(fr_mesh_t m, double *R, int on_device);
 
-/* Advance the state by n_steps explicit Runge-Kutta steps of size dt (enum fr_scheme). Every
- * stage is three kernels: the element pre-pass (solution and broken gradient to the faces),
- * the face kernel (common state, BR2 common gradient and common normal flux, once per face
- * point) and the volume kernel (corrected gradient, flux divergence and correction, and the
- * RK register update). Enqueued on the stream; returns without waiting. */
+/* Advance the state by n_steps explicit Runge-Kutta steps of size dt (enum fr_scheme). A stage
+ * is the element pre-pass (solution and broken gradient to the faces), the face kernel (common
+ * state, BR2 common gradient and common normal flux, once per face point) and the volume kernel
+ * (corrected gradient, flux divergence and correction, and the RK register update). With the
+ * fused pre-pass (fr_set_fusion, on by default) the run's first stage launches all three and
+ * every later stage two: its pre-pass was done by the previous stage's volume kernel. Enqueued
+ * on the stream; returns without waiting. */
 int fr_rk_step(fr_mesh_t m, double dt, int scheme, int n_steps);
 
 /* Kinetic-energy diagnostics of the current state (a quadrature over the mesh with the

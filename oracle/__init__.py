@@ -14,8 +14,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# FR_ORACLE_LIB_PATH selects another build of the same source (the sanitizer builds below)
+LIB_PATH = os.environ.get("FR_ORACLE_LIB_PATH") or os.path.join(_HERE, "liboracle.so")
 SRC = os.path.join(_HERE, "fr_oracle.cpp")
+SANITIZERS = {"address,undefined", "thread"}
 
 PREC = {"f64": 0, "ld": 1, "f32": 2}
 FLUX = {"rusanov": 0, "roe": 1}
@@ -24,8 +26,22 @@ SCHEME = {"rk4": 0, "lsrk45": 1, "ssprk104": 2}
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with g++ (OpenMP, no fast-math, no FMA contraction)."""
+def build(force: bool = True, sanitize: str = "") -> str:
+    """Compile liboracle.so with g++ (OpenMP, no fast-math, no FMA contraction).
+
+    sanitize = "address,undefined" or "thread": an instrumented build, liboracle_<name>.so, with
+    the ROCm clang++ and its OpenMP runtime (whose sanitizer runtimes the process preloads; the
+    thread sanitizer runs with the runtime's OMPT race-detection tool). Load it with
+    FR_ORACLE_LIB_PATH."""
+    if sanitize:
+        if sanitize not in SANITIZERS:
+            raise ValueError(f"sanitize must be one of {sorted(SANITIZERS)}")
+        out = os.path.join(_HERE, "liboracle_" + sanitize.replace(",", "_") + ".so")
+        cmd = ["/opt/rocm/llvm/bin/clang++", "-std=c++17", "-O1", "-g", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-fno-omit-frame-pointer", "-fsanitize=" + sanitize, "-o", out + ".tmp", SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+        return out
     if force or not os.path.exists(LIB_PATH):
         cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
                "-o", LIB_PATH + ".tmp", SRC]

@@ -26,17 +26,22 @@ FLAGS = [
 ]
 
 
-def object_path(src: str) -> str:
-    return os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+# host-side sanitizers only (the device code is not instrumented): each flag behind -Xarch_host
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
 
 
-def compile_command(src: str) -> list:
-    return ["hipcc", *FLAGS, "-c", "-o", object_path(src), src]
+def object_path(src: str, san: bool = False) -> str:
+    return os.path.join(OBJ_DIR, ("san_" if san else "") + os.path.basename(src) + ".o")
 
 
-def link_command(out: str = LIB) -> list:
-    return ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", out,
-            *[object_path(s) for s in SOURCES]]
+def compile_command(src: str, san: bool = False) -> list:
+    return ["hipcc", *FLAGS, *(SAN_FLAGS if san else []), "-c", "-o", object_path(src, san), src]
+
+
+def link_command(out: str = LIB, san: bool = False) -> list:
+    return ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *(SAN_FLAGS if san else []),
+            "-o", out, *[object_path(s, san) for s in SOURCES]]
 
 
 def hipcc_command(out: str = LIB) -> list:
@@ -44,7 +49,10 @@ def hipcc_command(out: str = LIB) -> list:
     return ["hipcc", *FLAGS, "-shared", "-o", out, *SOURCES]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Build libfr.so; sanitize=True builds _build/libfr_san.so instead, with the host code under
+    the address and undefined-behaviour sanitizers (load it with FR_LIB_PATH, the clang ASan
+    runtime preloaded)."""
     os.makedirs(OBJ_DIR, exist_ok=True)
 
     def run(cmd):
@@ -53,14 +61,15 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
 
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        for f in [ex.submit(run, compile_command(s)) for s in SOURCES]:
+        for f in [ex.submit(run, compile_command(s, sanitize)) for s in SOURCES]:
             f.result()
-    tmp = LIB + ".tmp"
-    run(link_command(tmp))
-    os.replace(tmp, LIB)
-    return LIB
+    out = os.path.join(OBJ_DIR, "libfr_san.so") if sanitize else LIB
+    tmp = out + ".tmp"
+    run(link_command(tmp, sanitize))
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv[1:])
     sys.exit(0)

@@ -1547,14 +1547,19 @@ int fr_autotune(fr_mesh_t m, int n_trials, double *ms) {
   int rc = FR_OK;
   double best = 1e300, t[12] = {0};
   int bi = 0;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(FR_ERR_HIP, "hipEventCreate");
+  // the scratch register starts at zero, so the timed stages (b = 0) store the state unchanged
+  // and the fused pre-pass writes the face data of the current state
+  if (hipMemsetAsync(tmp2, 0, M * sizeof(double), s) != hipSuccess) rc = fail(FR_ERR_HIP, "hipMemsetAsync");
+  if (rc == FR_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(FR_ERR_HIP, "hipEventCreate");
   for (int c = 0; c < 12 && rc == FR_OK; ++c) {
     dm.tile_epb = (c % 6) / 3;
     dm.tile_fbs = c % 3;
+    // a later LSRK stage (it reads and writes the register, as all but a run's first stage do)
     StageArgs st{};
     st.mode = kModeLSRK;
-    st.first = 1;
-    st.a = 0.0;
+    st.first = 0;
+    st.a = kLsA[1];
     st.b = 0.0;
     st.dt = 0.0;
     // c < 6: a stage with its own pre-pass; c >= 6: face + volume with the next pre-pass (the

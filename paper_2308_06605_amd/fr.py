@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfr.so")
+# FR_LIB_PATH selects another build of the same sources (the host-sanitizer build of build.py)
+LIB_PATH = os.environ.get("FR_LIB_PATH") or os.path.join(_HERE, "libfr.so")
 
 FR_OK = 0
 ERRORS = {-1: "FR_ERR_ARG", -2: "FR_ERR_MESH", -3: "FR_ERR_HIP", -4: "FR_ERR_OOM",

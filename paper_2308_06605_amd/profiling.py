@@ -1,10 +1,18 @@
-"""Turn rocprofv3 counter CSVs into a per-kernel HBM traffic summary.
+"""Turn rocprofv3 counter CSVs into per-kernel summaries.
 
-Usage (after two `rocprofv3 --pmc` runs of bench.py with --copy-calibration, one collecting
+HBM traffic (after two `rocprofv3 --pmc` runs of bench.py with --copy-calibration, one collecting
 FETCH_SIZE and one WRITE_SIZE):
 
   python -m paper_2308_06605_amd.profiling --fetch <dir>/run_counter_collection.csv \\
       --write <dir>/run_counter_collection.csv --calib-bytes 268435456 --out <summary.json>
+
+Other counters (any number of `--pmc` passes over the same command):
+
+  python -m paper_2308_06605_amd.profiling counters <csv> [<csv> ...] --out <summary.md>
+
+gives per kernel the mean of every counter over the kernel's dispatches and the derived ratios
+the design notes use (VALU and LDS instructions per wave, LDS bank conflicts per LDS
+instruction, waves resident per CU, LDS and VALU busy fractions).
 
 Each counter is averaged per kernel over its dispatches (KiB per dispatch) and scaled by the
 factor that makes the calibration copy (a plain device-to-device copy of --calib-bytes bytes)
@@ -88,7 +96,72 @@ def summarize(fetch_csv: str, write_csv: str, calib_bytes: int, prec: str = "fp6
             "calibration_copy_bytes": calib_bytes, "kernels": kernels}
 
 
+def per_kernel_counters(paths):
+    """{kernel: {counter: mean value per dispatch}} over the given counter-collection CSVs."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = short_name(r["Kernel_Name"])
+                if not k.startswith("k_"):
+                    continue
+                vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items()}
+
+
+def derived(c: dict) -> dict:
+    """Ratios of one kernel's counters (per dispatch means); only those whose inputs exist."""
+    out = {}
+    w = c.get("SQ_WAVES")
+    if w:
+        for name in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+                     "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_MFMA"):
+            if name in c:
+                out[name.replace("SQ_INSTS_", "") + " per wave"] = c[name] / w
+    if c.get("SQ_INSTS_LDS") and "SQ_LDS_BANK_CONFLICT" in c:
+        out["LDS bank-conflict cycles per LDS instruction"] = c["SQ_LDS_BANK_CONFLICT"] / c["SQ_INSTS_LDS"]
+    if c.get("SQ_BUSY_CYCLES") and "SQ_WAVE_CYCLES" in c:
+        # wave-cycles summed over waves (counted per SE, in units of 4 cycles on this part) over
+        # busy cycles: mean resident waves
+        out["mean resident waves (wave cycles / busy cycles)"] = c["SQ_WAVE_CYCLES"] / c["SQ_BUSY_CYCLES"]
+    for name in ("SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_WAIT_INST_LDS", "SQ_WAIT_ANY"):
+        if name in c and c.get("SQ_WAVE_CYCLES"):
+            out[name.replace("SQ_", "") + " / wave cycles"] = c[name] / c["SQ_WAVE_CYCLES"]
+    return out
+
+
+def counters_markdown(paths, title: str, command: str) -> str:
+    data = per_kernel_counters(paths)
+    lines = [f"# {title}", "", f"Command: `{command}`", "",
+             "Mean per dispatch of each counter, then derived ratios.", ""]
+    for k in sorted(data):
+        lines.append(f"## {k}")
+        lines.append("")
+        lines.append("| counter | value |")
+        lines.append("|---|---|")
+        for name in sorted(data[k]):
+            lines.append(f"| {name} | {data[k][name]:.6g} |")
+        for name, v in derived(data[k]).items():
+            lines.append(f"| *{name}* | {v:.4g} |")
+        lines.append("")
+    return "\n".join(lines)
+
+
 def main():
+    import sys
+
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        ap = argparse.ArgumentParser(prog="profiling counters")
+        ap.add_argument("csv", nargs="+")
+        ap.add_argument("--title", default="Kernel counters")
+        ap.add_argument("--command", default="")
+        ap.add_argument("--out", required=True)
+        a = ap.parse_args(sys.argv[2:])
+        text = counters_markdown(a.csv, a.title, a.command)
+        with open(a.out, "w") as f:
+            f.write(text + "\n")
+        print(text)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
