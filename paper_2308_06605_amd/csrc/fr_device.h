@@ -257,6 +257,47 @@ __device__ __forceinline__ void face_store(T v, T *p) {
   }
 }
 
+// A thread's point index along xi_2 within its element. With one element per block and N*N = 64
+// points per xi_2-plane (p = 7), each wavefront covers exactly one plane, so the index is the same
+// on every lane; saying so lets the compiler keep the operator row D[i2][.] in scalar registers.
+template <int N, int EPB>
+__device__ __forceinline__ int plane_index(int t) {
+  if constexpr (N * N == 64 && EPB == 1) return __builtin_amdgcn_readfirstlane(t / (N * N));
+  else return t / (N * N);
+}
+
+// Face interpolation of a point-ordered element array src: sum over c = 0..N-1, in ascending
+// order, of ell[c] src[line_pt(d, c, a, b)], the line normal to face f (direction d = f/2) through
+// its face point (a, b), with ell = l(-1) or l(+1) by the face's side. f must be the same on every
+// lane of the wavefront (the p = 7 kernels give each wavefront one face of 64 points): the
+// direction then picks one of three loops whose LDS strides are constants, and ell is read
+// through scalar loads. The sums are those of the per-lane form, term for term.
+template <int N, typename T, typename C>
+__device__ __forceinline__ T face_sum_uniform(int f, int a, int b, const T *src, const C *lm, const C *lp) {
+  const C *ell = (f & 1) ? lp : lm;
+  const int d = f >> 1;
+  T acc = 0;
+  if (d == 0) {
+    const T *q = src + N * (a + N * b);
+#pragma unroll
+    for (int c = 0; c < N; ++c) acc += ell[c] * q[c];
+  } else if (d == 1) {
+    const T *q = src + a + N * N * b;
+#pragma unroll
+    for (int c = 0; c < N; ++c) acc += ell[c] * q[c * N];
+  } else {
+    const T *q = src + a + N * b;
+#pragma unroll
+    for (int c = 0; c < N; ++c) acc += ell[c] * q[c * N * N];
+  }
+  return acc;
+}
+
+// One wavefront per face of the element (64 face points, one per lane): p = 7 with one element
+// per block, where the kernels take their face loops as wave-uniform (value, face) tasks.
+template <int NFP, int EPB>
+constexpr bool kWavePerFace = NFP == 64 && EPB == 1;
+
 // index of solution point with coordinate c along direction d and (a, b) along the face's
 // tangential directions (increasing axis order)
 template <int N>

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) v
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
-  const int i0 = t % N, i1 = (t / N) % N, i2 = t / (N * N);
+  const int i0 = t % N, i1 = (t / N) % N, i2 = plane_index<N, EPB>(t);
   if (act) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) sU[slot][v][t] = real(X[(e * 5 + v) * NS + t]);
@@ -84,10 +84,22 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) v
   }
   __syncthreads();
   if (!act) return;
+  constexpr int NVAL = VISC ? 20 : 5;
+  if constexpr (kWavePerFace<NFP, EPB>) {
+    // p = 7: wave-uniform tasks (value, face), the face's 64 points on the lanes
+    const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int a = lane % N, b = lane / N;
+    for (int k = wv; k < NVAL * 6; k += NS / 64) {
+      const int val = k / 6, f = k - 6 * val;
+      const real *src = val < 5 ? &sU[slot][val][0] : &sG[slot][(val - 5) % (NG > 0 ? NG : 1)][0];
+      face_store<NFP>(face_sum_uniform<N>(f, a, b, src, ops.lm, ops.lp),
+                      &face[((e * 6 + f) * 20 + val) * NFP + lane]);
+    }
+    return;
+  }
   // items are (group of GV values, face point); consecutive threads write consecutive points
   // of one face. With more face points than threads (p <= 4) one item carries all 20 values,
   // which amortises the index arithmetic; at higher degree groups of 5 balance the threads.
-  constexpr int NVAL = VISC ? 20 : 5;
   constexpr int GV = (NF > NS || !VISC) ? NVAL : 5;
   constexpr int NGRP = NVAL / GV;
   for (int q = t; q < NGRP * NF; q += NS) {
@@ -284,7 +296,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
-  const int idx[3] = {t % N, (t / N) % N, t / (N * N)};
+  const int idx[3] = {t % N, (t / N) % N, plane_index<N, EPB>(t)};
   real *sU = sUall[slot];
   real *sJ = sJall[slot];
 
@@ -445,16 +457,26 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
         }
         div[v] += acc;
       }
-      for (int fp = t; fp < 2 * NFP; fp += NS) {
-        const int f = 2 * d + fp / NFP, kk = fp % NFP;
-        const int a = kk % N, b = kk / N;
-        const real *ell = (f & 1) ? ops.lp : ops.lm;
+      // the transformed flux at the two faces normal to d: at p = 7 wave-uniform tasks (value,
+      // face) over all threads, otherwise a thread per face point
+      if constexpr (kWavePerFace<NFP, EPB>) {
+        const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+        for (int k = wv; k < 10; k += NS / 64) {
+          const int v = k >> 1, f = 2 * d + (k & 1);
+          sJ[v * NF + f * NFP + lane] -= face_sum_uniform<N>(f, lane % N, lane / N, &sF[v * NS], ops.lm, ops.lp);
+        }
+      } else {
+        for (int fp = t; fp < 2 * NFP; fp += NS) {
+          const int f = 2 * d + fp / NFP, kk = fp % NFP;
+          const int a = kk % N, b = kk / N;
+          const real *ell = (f & 1) ? ops.lp : ops.lm;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          real acc = 0;
+          for (int v = 0; v < 5; ++v) {
+            real acc = 0;
 #pragma unroll
-          for (int c = 0; c < N; ++c) acc += ell[c] * sF[v * NS + line_pt<N>(d, c, a, b)];
-          sJ[v * NF + f * NFP + kk] -= acc;
+            for (int c = 0; c < N; ++c) acc += ell[c] * sF[v * NS + line_pt<N>(d, c, a, b)];
+            sJ[v * NF + f * NFP + kk] -= acc;
+          }
         }
       }
     }
@@ -528,6 +550,58 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       }
     }
   };
+  if constexpr (kWavePerFace<NFP, EPB>) {
+    // p = 7: wave-uniform tasks (value or gradient component, face), 64 face points per task
+    const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int a = lane % N, b = lane / N;
+    if (act) {
+      for (int k = wv; k < 5 * 6; k += NS / 64) {
+        const int v = k / 6, f = k - 6 * v;
+        face_store<NFP>(face_sum_uniform<N>(f, a, b, &sU[v * NS], ops.lm, ops.lp),
+                        &face[((e * 6 + f) * 20 + v) * NFP + lane]);
+      }
+    }
+    if (GRAD) {
+      if (act) load_metric();
+#pragma unroll
+      for (int v0 = 0; v0 < 5; v0 += VPC) {
+        const int nv = 5 - v0 < VPC ? 5 - v0 : VPC;
+        if (act) {
+#pragma unroll UNW
+          for (int w = 0; w < VPC; ++w) {
+            if (w < nv) {
+              const int v = v0 + w;
+              real d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+              for (int c = 0; c < N; ++c) {
+                d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+                d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+                d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+              }
+#pragma unroll
+              for (int ii = 0; ii < 3; ++ii) {
+                real g = jb[ii] * d0;
+                g += jb[3 + ii] * d1;
+                g += jb[6 + ii] * d2;
+                sJ[(w * 3 + ii) * NS + t] = iJb * g;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (act) {
+          for (int k = wv; k < 3 * nv * 6; k += NS / 64) {
+            const int ci = k / 6, f = k - 6 * ci;
+            const int v = v0 + ci / 3, ii = ci - (ci / 3) * 3;
+            face_store<NFP>(face_sum_uniform<N>(f, a, b, &sJ[ci * NS], ops.lm, ops.lp),
+                            &face[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + lane]);
+          }
+        }
+        __syncthreads();
+      }
+    }
+    return;
+  }
   if (GRAD && VPC == 5) {
     if (act) {
       load_metric();

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *_
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
-  const int i0 = t % N, i1 = (t / N) % N, i2 = t / (N * N);
+  const int i0 = t % N, i1 = (t / N) % N, i2 = plane_index<N, EPB>(t);
   if (act) {
     const double x0 = X[(e * 5 + 0) * NS + t], x4 = X[(e * 5 + 4) * NS + t];
     sU[slot][0][t] = float(x0 - ref.rho_d);
@@ -172,6 +172,26 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *_
   }
   __syncthreads();
   if (!act) return;
+  if constexpr (kWavePerFace<NFP, EPB>) {
+    // p = 7: wave-uniform tasks (value, face), the face's 64 points on the lanes: U' (5), the
+    // gradient (15), then the FP64 momentum (3)
+    const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int a = lane % N, b = lane / N;
+    constexpr int NV = VISC ? 20 : 5;
+    for (int k = wv; k < (NV + 3) * 6; k += NS / 64) {
+      const int val = k / 6, f = k - 6 * val;
+      if (val < NV) {
+        const float *src = val < 5 ? &sU[slot][val][0] : &sG[slot][(val - 5) % NG][0];
+        face_store<NFP>(face_sum_uniform<N>(f, a, b, src, ops.lm, ops.lp),
+                        &face32[((e * 6 + f) * 20 + val) * NFP + lane]);
+      } else {
+        const int i = val - NV;
+        face_store<NFP>(face_sum_uniform<N>(f, a, b, &sM[slot][i][0], opsd.lm, opsd.lp),
+                        &facem[((e * 6 + f) * 3 + i) * NFP + lane]);
+      }
+    }
+    return;
+  }
   for (int fp = t; fp < NF; fp += NS) {
     const int f = fp / NFP, kk = fp - f * NFP;
     const int a = kk % N, b = kk / N, d = f >> 1;
@@ -361,7 +381,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
-  const int idx[3] = {t % N, (t / N) % N, t / (N * N)};
+  const int idx[3] = {t % N, (t / N) % N, plane_index<N, EPB>(t)};
   float *sU = sUall[slot];
   double *sM = sMall[slot];
   float *sJ = sJall[slot];
@@ -516,6 +536,17 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
         }
         divm += acc;
       }
+      if constexpr (kWavePerFace<NFP, EPB>) {
+        // p = 7: wave-uniform tasks (component, face of direction d), component 4 the FP64 mass
+        const int lane = t & 63, wv = __builtin_amdgcn_readfirstlane(t >> 6);
+        for (int k = wv; k < 10; k += NS / 64) {
+          const int v = k >> 1, f = 2 * d + (k & 1);
+          if (v < 4)
+            sJ[v * NF + f * NFP + lane] -= face_sum_uniform<N>(f, lane % N, lane / N, &sF[v * NS], ops.lm, ops.lp);
+          else
+            sJm[f * NFP + lane] -= face_sum_uniform<N>(f, lane % N, lane / N, sM, opsd.lm, opsd.lp);
+        }
+      } else
       for (int fp = t; fp < 2 * NFP; fp += NS) {
         const int f = 2 * d + fp / NFP, kk = fp % NFP;
         const int a = kk % N, b = kk / N;
@@ -640,7 +671,18 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
     }
     return;
   }
+  // p = 7: the face loops as wave-uniform tasks (value, face), 64 face points per task
+  constexpr bool WPF = kWavePerFace<NFP, EPB>;
+  const int lane = t & 63, wv = WPF ? __builtin_amdgcn_readfirstlane(t >> 6) : 0;
+  const int la = lane % N, lb = lane / N;
   if (act) {
+    if constexpr (WPF) {
+      for (int k = wv; k < 5 * 6; k += NS / 64) {
+        const int v = k / 6, f = k - 6 * v;
+        face_store<NFP>(face_sum_uniform<N>(f, la, lb, &sU[v * NS], ops.lm, ops.lp),
+                        &face32[((e * 6 + f) * 20 + v) * NFP + lane]);
+      }
+    } else
     for (int q = t; q < 5 * NF; q += NS) {
       const int v = q / NF;
       int f, kk, b0, stride;
@@ -683,7 +725,21 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
       }
     }
     __syncthreads();
-    if (act) {
+    if (act && WPF) {
+      for (int k = wv; k < (r < 3 ? 6 : 0) + 3 * nv * 6; k += NS / 64) {
+        if (r < 3 && k < 6) {
+          face_store<NFP>(face_sum_uniform<N>(k, la, lb, sM, opsd.lm, opsd.lp),
+                          &facem[((e * 6 + k) * 3 + r) * NFP + lane]);
+          continue;
+        }
+        const int kg = r < 3 ? k - 6 : k;
+        const int ci = kg / 6, f = kg - 6 * ci;
+        const int v = v0 + ci / 3, ii = ci - (ci / 3) * 3;
+        face_store<NFP>(face_sum_uniform<N>(f, la, lb, &sJ[ci * NS], ops.lm, ops.lp),
+                        &face32[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + lane]);
+      }
+    }
+    if (act && !WPF) {
       if (r < 3) {
         for (int fp = t; fp < NF; fp += NS) {
           int f, kk, b0, stride;
