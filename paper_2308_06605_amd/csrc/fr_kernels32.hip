@@ -125,7 +125,7 @@ __device__ __forceinline__ void full_state(const float Up[5], const Ref32 &r, fl
 // K1 (FP32 form): U' and its broken gradient to the faces in FP32, momentum to the faces in FP64
 // ------------------------------------------------------------------------------------------
 template <int P, bool VISC, int EPBX>
-__global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *__restrict__ X,
+__device__ __forceinline__ void prepass32_body(int64_t blk, const double *__restrict__ X,
                                                                  const float *__restrict__ geo32,
                                                                  float *__restrict__ face32,
                                                                  double *__restrict__ facem, int64_t E,
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *_
   __shared__ double sM[EPB][3][NS];
   __shared__ float sG[EPB][NG][NS];
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
-  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const int64_t e = (int64_t)blk * EPB + slot;
   const bool act = e < E;
   const int i0 = t % N, i1 = (t / N) % N, i2 = plane_index<N, EPB>(t);
   if (act) {
@@ -225,6 +225,15 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *_
   }
 }
 
+template <int P, bool VISC, int EPBX>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32(const double *__restrict__ X,
+                                                                 const float *__restrict__ geo32,
+                                                                 float *__restrict__ face32,
+                                                                 double *__restrict__ facem, int64_t E,
+                                                                 OpsT<float> ops, OpsT<double> opsd, Ref32 ref) {
+  prepass32_body<P, VISC, EPBX>(blockIdx.x, X, geo32, face32, facem, E, ops, opsd, ref);
+}
+
 // ------------------------------------------------------------------------------------------
 // K2 (FP32 form): common jump and flux per face point. Outputs
 //   fout32 [F][9][Nfp]: J' = (U'_R - U'_L)/2 (5), owner's momentum flux (3), reduced energy (1)
@@ -284,12 +293,12 @@ __device__ __forceinline__ void wall_face32(const float *srcL, const double *fg,
 }
 
 template <int P, bool VISC, int FBS>
-__global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32, const double *__restrict__ facem,
+__device__ __forceinline__ void face32_body(int64_t blk, const float *__restrict__ face32, const double *__restrict__ facem,
                                                 const double *__restrict__ fgeo, const FaceRec *__restrict__ ftab,
                                                 int64_t F, Phys<float> ph, Ref32 ref, int flux, float tw_gm1,
                                                 float cw, float *__restrict__ fout32, double *__restrict__ foutm) {
   constexpr int N = P + 1, NFP = N * N;
-  const int64_t gid = (int64_t)blockIdx.x * FBS + threadIdx.x;
+  const int64_t gid = (int64_t)blk * FBS + threadIdx.x;
   const int64_t fc = gid / NFP;
   if (fc >= F) return;
   const int kk = (int)(gid - fc * NFP);
@@ -349,6 +358,14 @@ __global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32
   __builtin_nontemporal_store(fc_rho + double(nm * Fr[0]), &foutm[fc * NFP + kk]);
 }
 
+template <int P, bool VISC, int FBS>
+__global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32, const double *__restrict__ facem,
+                                                const double *__restrict__ fgeo, const FaceRec *__restrict__ ftab,
+                                                int64_t F, Phys<float> ph, Ref32 ref, int flux, float tw_gm1,
+                                                float cw, float *__restrict__ fout32, double *__restrict__ foutm) {
+  face32_body<P, VISC, FBS>(blockIdx.x, face32, facem, fgeo, ftab, F, ph, ref, flux, tw_gm1, cw, fout32, foutm);
+}
+
 // ------------------------------------------------------------------------------------------
 // K3 (FP32 form): corrected gradient, reduced fluxes, divergence + correction in FP32 for
 // momentum and reduced energy, in FP64 for mass; R_E = R''_E + H_r R_rho; RK update in FP64.
@@ -358,7 +375,7 @@ __global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32
 // X, the stage's state, is the same array as out0 (LSRK45, SSP) or reg2 (RK4 after the first
 // stage), so X, out0, reg1 and reg2 carry no __restrict__.
 template <int P, bool VISC, int EPBX, bool PRE>
-__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) void k_volume32(
+__device__ __forceinline__ void volume32_body(int64_t blk,
     const double *X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
     const float *__restrict__ fout32, const double *__restrict__ foutm, int64_t E, OpsT<float> ops,
     OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *out0,
@@ -378,8 +395,14 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
   __shared__ double sMall[EPB][NMS];       // transformed mass flux of one direction
   __shared__ float sJall[EPB][NJ];
   __shared__ double sJmall[EPB][NF];       // mass flux along +xi_d, then its jump
+  // With the fused pre-pass at p = 3 and p = 7 the LDS left free at these kernels' occupancy
+  // (four blocks of four waves, two of eight) keeps the FP32 metric terms each thread converts
+  // from the FP64 ones it loaded (the same roundings as the FP32 geometry copy), so the tail does
+  // not read that copy from HBM again; each thread reads back its own terms (no barrier).
+  constexpr bool MST = PRE && VISC && (P == 3 || P == 7);
+  __shared__ float sMetall[EPB][MST ? 10 * NS : 1];
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
-  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
+  const int64_t e = (int64_t)blk * EPB + slot;
   const bool act = e < E;
   const int idx[3] = {t % N, (t / N) % N, plane_index<N, EPB>(t)};
   float *sU = sUall[slot];
@@ -394,6 +417,11 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
 #pragma unroll
     for (int c = 0; c < 9; ++c) jad[c] = geo[(e * 10 + c) * NS + t];
     iJd = geo[(e * 10 + 9) * NS + t];
+    if (MST) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sMetall[slot][c * NS + t] = float(jad[c]);
+      sMetall[slot][9 * NS + t] = float(iJd);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int fp = t + r * NS;
@@ -626,8 +654,8 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
       if (VISC) {
         float jb[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) jb[c] = geo32_again[(e * 10 + c) * NS + t];
-        const float iJb = geo32_again[(e * 10 + 9) * NS + t];
+        for (int c = 0; c < 9; ++c) jb[c] = MST ? sMetall[slot][c * NS + t] : geo32_again[(e * 10 + c) * NS + t];
+        const float iJb = MST ? sMetall[slot][9 * NS + t] : geo32_again[(e * 10 + 9) * NS + t];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           float d0 = 0, d1 = 0, d2 = 0;
@@ -697,8 +725,8 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
   float jb[9], iJb = 0;
   if (VISC && act) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) jb[c] = geo32_again[(e * 10 + c) * NS + t];
-    iJb = geo32_again[(e * 10 + 9) * NS + t];
+    for (int c = 0; c < 9; ++c) jb[c] = MST ? sMetall[slot][c * NS + t] : geo32_again[(e * 10 + c) * NS + t];
+    iJb = MST ? sMetall[slot][9 * NS + t] : geo32_again[(e * 10 + 9) * NS + t];
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -765,6 +793,16 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
     }
     __syncthreads();
   }
+}
+
+template <int P, bool VISC, int EPBX, bool PRE>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) void k_volume32(
+    const double *X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
+    const float *__restrict__ fout32, const double *__restrict__ foutm, int64_t E, OpsT<float> ops,
+    OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *out0,
+    double *reg1, double *reg2, float *__restrict__ face32,
+    double *__restrict__ facem, const float *geo32_again) {
+  volume32_body<P, VISC, EPBX, PRE>(blockIdx.x, X, geo, fref, fout32, foutm, E, ops, opsd, ph, ref, st, out0, reg1, reg2, face32, facem, geo32_again);
 }
 
 #define HIPCHK32(call)                                           \
