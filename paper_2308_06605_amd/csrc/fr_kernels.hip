@@ -40,7 +40,7 @@ using namespace frk;
 // K1: element pre-pass
 // ------------------------------------------------------------------------------------------
 template <int P, typename real, bool VISC, int EPBX>
-__device__ __forceinline__ void prepass_body(int64_t blk, const double *__restrict__ X,
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void k_prepass(const double *__restrict__ X,
                                                            const real *__restrict__ geo,
                                                            real *__restrict__ face, int64_t E,
                                                            OpsT<real> ops) {
@@ -50,7 +50,7 @@ __device__ __forceinline__ void prepass_body(int64_t blk, const double *__restri
   __shared__ real sU[EPB][5][NS];
   __shared__ real sG[EPB][NG > 0 ? NG : 1][NS];
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
-  const int64_t e = (int64_t)blk * EPB + slot;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
   const int i0 = t % N, i1 = (t / N) % N, i2 = plane_index<N, EPB>(t);
   if (act) {
@@ -120,14 +120,6 @@ __device__ __forceinline__ void prepass_body(int64_t blk, const double *__restri
   }
 }
 
-template <int P, typename real, bool VISC, int EPBX>
-__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) void k_prepass(const double *__restrict__ X,
-                                                           const real *__restrict__ geo,
-                                                           real *__restrict__ face, int64_t E,
-                                                           OpsT<real> ops) {
-  prepass_body<P, real, VISC, EPBX>(blockIdx.x, X, geo, face, E, ops);
-}
-
 // ------------------------------------------------------------------------------------------
 // K2: face kernel. One thread per face point of each face (owner side L): the common state,
 // the BR2 common gradient and the common normal flux, computed once per face point.
@@ -186,12 +178,12 @@ __device__ __forceinline__ void wall_face(const real *srcL, const real *fg, int 
 }
 
 template <int P, typename real, bool VISC, bool SGS, bool LDG, int FBS>
-__device__ __forceinline__ void face_body(int64_t blk, const real *__restrict__ face, const real *__restrict__ fgeo,
+__global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
                                               const FaceRec *__restrict__ ftab, int64_t F, Phys<real> ph,
                                               int flux, real *__restrict__ fout, const double *__restrict__ nut,
                                               real kt, real tau, real tw_gm1) {
   constexpr int N = P + 1, NFP = N * N;
-  const int64_t gid = (int64_t)blk * FBS + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * FBS + threadIdx.x;
   const int64_t fc = gid / NFP;
   if (fc >= F) return;
   const int kk = (int)(gid - fc * NFP);
@@ -276,14 +268,6 @@ __device__ __forceinline__ void face_body(int64_t blk, const real *__restrict__ 
   }
 }
 
-template <int P, typename real, bool VISC, bool SGS, bool LDG, int FBS>
-__global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const real *__restrict__ face, const real *__restrict__ fgeo,
-                                              const FaceRec *__restrict__ ftab, int64_t F, Phys<real> ph,
-                                              int flux, real *__restrict__ fout, const double *__restrict__ nut,
-                                              real kt, real tau, real tw_gm1) {
-  face_body<P, real, VISC, SGS, LDG, FBS>(blockIdx.x, face, fgeo, ftab, F, ph, flux, fout, nut, kt, tau, tw_gm1);
-}
-
 // ------------------------------------------------------------------------------------------
 // K3: volume kernel. Per element: gathers its faces' jumps and common fluxes into LDS, forms
 // the corrected gradient (g_DG correction by U^C - U), the pointwise flux F_inv - F_v, the
@@ -295,7 +279,7 @@ __global__ __launch_bounds__(FBS) FR_WPE_ATTR(FR_WPE_FACE(P)) void k_face(const 
 // X, the stage's state, is the same array as out0 (LSRK45, SSP) or reg2 (RK4 after the first
 // stage), so X, out0, reg1 and reg2 carry no __restrict__.
 template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX, bool PRE>
-__device__ __forceinline__ void volume_body(int64_t blk,
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS, PRE)) void k_volume(
     const double *X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
     const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
     double *out0, double *reg1, double *reg2,
@@ -315,7 +299,7 @@ __device__ __forceinline__ void volume_body(int64_t blk,
   constexpr int NMS = PRE && VISC && !LDG && kWavePerFace<NFP, EPB> && sizeof(real) == 8 ? 7 : 0;
   __shared__ real sMet[NMS > 0 ? NMS : 1][NMS > 0 ? NS : 1];
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
-  const int64_t e = (int64_t)blk * EPB + slot;
+  const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
   const int idx[3] = {t % N, (t / N) % N, plane_index<N, EPB>(t)};
   real *sU = sUall[slot];
@@ -713,15 +697,6 @@ __device__ __forceinline__ void volume_body(int64_t blk,
       __syncthreads();
     }
   }
-}
-
-template <int P, typename real, bool VISC, bool SGS, bool LDG, int EPBX, bool PRE>
-__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS, PRE)) void k_volume(
-    const double *X, const real *__restrict__ geo, const FaceRef *__restrict__ fref,
-    const real *__restrict__ fout, int64_t E, OpsT<real> ops, Phys<real> ph, StageArgs st,
-    double *out0, double *reg1, double *reg2,
-    const double *__restrict__ nut, real kt, real *__restrict__ face, const real *geo_again) {
-  volume_body<P, real, VISC, SGS, LDG, EPBX, PRE>(blockIdx.x, X, geo, fref, fout, E, ops, ph, st, out0, reg1, reg2, nut, kt, face, geo_again);
 }
 
 

@@ -125,7 +125,7 @@ __device__ __forceinline__ void full_state(const float Up[5], const Ref32 &r, fl
 // K1 (FP32 form): U' and its broken gradient to the faces in FP32, momentum to the faces in FP64
 // ------------------------------------------------------------------------------------------
 template <int P, bool VISC, int EPBX>
-__device__ __forceinline__ void prepass32_body(int64_t blk, const double *__restrict__ X,
+__device__ __forceinline__ void prepass32_body(unsigned blk, const double *__restrict__ X,
                                                                  const float *__restrict__ geo32,
                                                                  float *__restrict__ face32,
                                                                  double *__restrict__ facem, int64_t E,
@@ -293,7 +293,7 @@ __device__ __forceinline__ void wall_face32(const float *srcL, const double *fg,
 }
 
 template <int P, bool VISC, int FBS>
-__device__ __forceinline__ void face32_body(int64_t blk, const float *__restrict__ face32, const double *__restrict__ facem,
+__device__ __forceinline__ void face32_body(unsigned blk, const float *__restrict__ face32, const double *__restrict__ facem,
                                                 const double *__restrict__ fgeo, const FaceRec *__restrict__ ftab,
                                                 int64_t F, Phys<float> ph, Ref32 ref, int flux, float tw_gm1,
                                                 float cw, float *__restrict__ fout32, double *__restrict__ foutm) {
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(FBS) void k_face32(const float *__restrict__ face32
 // X, the stage's state, is the same array as out0 (LSRK45, SSP) or reg2 (RK4 after the first
 // stage), so X, out0, reg1 and reg2 carry no __restrict__.
 template <int P, bool VISC, int EPBX, bool PRE>
-__device__ __forceinline__ void volume32_body(int64_t blk,
+__device__ __forceinline__ void volume32_body(unsigned blk,
     const double *X, const double *__restrict__ geo, const FaceRef *__restrict__ fref,
     const float *__restrict__ fout32, const double *__restrict__ foutm, int64_t E, OpsT<float> ops,
     OpsT<double> opsd, Phys<float> ph, Ref32 ref, StageArgs st, double *out0,
