@@ -258,6 +258,18 @@ typedef struct fr_batch_s *fr_batch_t;
 int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int scheme, void *hip_stream,
                     fr_batch_t *out);
 
+/* fr_batch_create with flags. FR_BATCH_MULTI (the default of fr_batch_create): the viscous
+ * FP32-form meshes without closure or LDG are grouped by degree, fusion setting and tiles, and
+ * each group's step is one launch per kernel and stage covering all its meshes: block b of the
+ * grid is an element block or a face block of one of the group's meshes (found from prefix sums
+ * of the meshes' block counts) and runs the arithmetic of the single-mesh kernel's block, with
+ * that mesh's arguments (state, geometry, step size, physics, reference state) from a device
+ * table. Every other mesh, and every mesh when flags = 0, steps on a graph branch of its own.
+ * Results are bitwise those of fr_rk_step either way. */
+#define FR_BATCH_MULTI 1
+int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int scheme, void *hip_stream,
+                       int32_t flags, fr_batch_t *out);
+
 /* Enqueue n_steps replays of the captured step on the batch's stream (returns without waiting). */
 int fr_batch_step(fr_batch_t b, int n_steps);
 int fr_batch_set_stream(fr_batch_t b, void *hip_stream);

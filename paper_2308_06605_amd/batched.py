@@ -11,10 +11,14 @@ dt = 1.5 h / ((|u| + c)(p + 1)(p + 2) 1.7). Each mesh's tile shapes come from th
 direction is then (1, 0.5, 0.25) normalised), --fp64 runs the FP64 kernels, --no-autotune keeps the
 default tiles.
 
-Two ways to run the same steps are timed on the same meshes and state:
-  sequential  fr_rk_step on each mesh in turn (15 kernel launches per mesh and step),
-  batch       one captured HIP graph per step (fr_batch_step): every mesh on its own branch.
-Throughput is the total DOF-updates per second per RK stage.
+Three ways to run the same steps are timed on the same meshes and state:
+  sequential  fr_rk_step on each mesh in turn (11 to 15 kernel launches per mesh and step),
+  branches    one captured HIP graph per step, every mesh on a graph branch of its own,
+  multi       one captured HIP graph per step in which each degree's meshes are stepped by the
+              multi-mesh kernels: per stage one face and one volume launch covering all of them,
+              block b of a launch being some mesh's element or face block (fr_batch_create).
+Throughput is the total DOF-updates per second per RK stage; the roofline fraction is the
+meshes' summed two-pass minimum bytes per stage over the stage time at 8 TB/s.
 
   python -m paper_2308_06605_amd.batched [--n-mesh 48] [--steps 10] [--seed 0]
 """
@@ -108,23 +112,36 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune
     torch.cuda.synchronize()
     ms_seq = e0.elapsed_time(e1) / steps
     U_seq = [g.get_state() for g in meshes]
-    # batch graph
-    reset()
-    t1 = time.time()
-    b = fr.Batch(meshes, dts, "lsrk45")
-    capture_s = time.time() - t1
-    b.step(warmup)
-    reset()
-    e0.record(stream)
-    b.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_batch = e0.elapsed_time(e1) / steps
-    same = all(np.array_equal(g.get_state(), u) for g, u in zip(meshes, U_seq))
+    # the two captured forms
+    timed = {}
+    same = True
+    for name, multi in (("branches", False), ("multi", True)):
+        reset()
+        t1 = time.time()
+        b = fr.Batch(meshes, dts, "lsrk45", multi=multi)
+        capture_s = time.time() - t1
+        b.step(warmup)
+        reset()
+        e0.record(stream)
+        b.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        same = same and all(np.array_equal(g.get_state(), u) for g, u in zip(meshes, U_seq))
+        b.close()
+        timed[name] = {"ms_per_step": ms, "dof_updates_per_s": dof * stages / (ms * 1e-3), "capture_s": capture_s}
     finite = all(np.isfinite(u).all() for u in U_seq)
-    b.close()
     for g in meshes:
         g.close()
+    # the two-pass minimum bytes per stage of every mesh (SURVEY's per-element rule)
+    stage_bytes = 0
+    for s in specs:
+        n_, p_ = s["n"], s["p"]
+        Ns, Nf = (p_ + 1) ** 3, 6 * (p_ + 1) ** 2
+        per = 8 * (45 * Ns + 44 * Nf) if prec == "fp64" else 8 * 25 * Ns + 4 * (20 * Ns + 44 * Nf)
+        stage_bytes += per * n_ ** 3
+    for rec in [timed["branches"], timed["multi"]]:
+        rec["roofline_frac"] = stage_bytes / (rec["ms_per_step"] / stages * 1e-3) / 8e12
     geo = "channel meshes (isothermal walls in y)" if walls else "periodic box meshes"
     out = {
         "workload": f"{n_mesh} {geo}, log-uniform 8^3..40^3 elements, p in 2..5, Mach 0.2-0.5, "
@@ -132,13 +149,17 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune
                     f"{'autotuned' if autotune else 'default'} tiles, seed {seed}",
         "n_mesh": n_mesh, "dof": int(dof), "elements": int(sum(g.E for g in meshes)),
         "steps": steps, "stages_per_step": stages,
-        "sequential": {"ms_per_step": ms_seq, "dof_updates_per_s": dof * stages / (ms_seq * 1e-3)},
-        "batch_graph": {"ms_per_step": ms_batch, "dof_updates_per_s": dof * stages / (ms_batch * 1e-3),
-                        "capture_s": capture_s},
-        "speedup": ms_seq / ms_batch, "bitwise_equal": bool(same), "finite": bool(finite),
+        "sequential": {"ms_per_step": ms_seq, "dof_updates_per_s": dof * stages / (ms_seq * 1e-3),
+                       "roofline_frac": stage_bytes / (ms_seq / stages * 1e-3) / 8e12},
+        "batch_branches": timed["branches"], "batch_multi": timed["multi"],
+        "stage_min_bytes": stage_bytes,
+        "speedup_multi_vs_sequential": ms_seq / timed["multi"]["ms_per_step"],
+        "speedup_multi_vs_branches": timed["branches"]["ms_per_step"] / timed["multi"]["ms_per_step"],
+        "bitwise_equal": bool(same), "finite": bool(finite),
         "setup_s": setup_s, "autotune_s": autotune_s,
         "tiles_chosen": {f"{e},{f}": sum(1 for t in tiles if tuple(t) == (e, f)) for e in (0, 1) for f in (0, 1, 2)},
         "fused_prepass": sum(fused),
+        "multi_groups": len({(s["p"], fz, tuple(t)) for s, t, fz in zip(specs, tiles, fused)}),
         "meshes": [dict(s, dt=dt, tiles=list(t), fused=fz) for s, dt, t, fz in zip(specs, dts, tiles, fused)],
     }
     return out

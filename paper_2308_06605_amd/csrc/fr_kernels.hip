@@ -22,6 +22,7 @@
 // computes the per-element features (k_sgs_features) and the network's eddy viscosity.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -1791,6 +1792,7 @@ int fr_get_eddy_viscosity(fr_mesh_t m, double *nu) {
 struct fr_batch_s {
   uint64_t magic;
   std::vector<fr_mesh_t> meshes;
+  std::vector<Group32 *> groups;  // meshes stepped by the multi-mesh kernels, one group per degree
   hipStream_t stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1805,7 +1807,13 @@ extern "C" {
 
 int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int scheme, void *hip_stream,
                     fr_batch_t *out) {
+  return fr_batch_create_ex(meshes, n, dt, scheme, hip_stream, FR_BATCH_MULTI, out);
+}
+
+int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int scheme, void *hip_stream,
+                       int32_t flags, fr_batch_t *out) {
   if (!out) return fail(FR_ERR_ARG, "out is NULL");
+  if (flags & ~FR_BATCH_MULTI) return fail(FR_ERR_ARG, "unknown batch flags");
   *out = nullptr;
   if (!meshes || !dt || n < 1) return fail(FR_ERR_ARG, "need n >= 1 meshes and their dt");
   if (scheme != FR_RK4 && scheme != FR_LSRK45 && scheme != FR_SSPRK104) return fail(FR_ERR_ARG, "unknown scheme");
@@ -1821,9 +1829,49 @@ int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int sc
     int rc = ensure_registers(meshes[i]->dm, scheme);
     if (rc) return rc;
   }
+  // the meshes the multi-mesh kernels take, grouped by (degree, fusion, tiles), so that every
+  // mesh keeps its own tiles; every other mesh steps on a branch of its own
+  std::vector<Group32 *> groups;
+  std::vector<int> alone;
+  {
+    std::vector<std::vector<int>> members;
+    std::vector<std::array<int, 4>> keys;
+    for (int i = 0; i < n; ++i) {
+      const DeviceMesh &dm = meshes[i]->dm;
+      if (!(flags & FR_BATCH_MULTI) || !group32_eligible(dm)) {
+        alone.push_back(i);
+        continue;
+      }
+      const std::array<int, 4> key{dm.p, dm.fuse ? 1 : 0, dm.tile_epb, dm.tile_fbs};
+      size_t k = 0;
+      while (k < keys.size() && keys[k] != key) ++k;
+      if (k == keys.size()) {
+        keys.push_back(key);
+        members.push_back({});
+      }
+      members[k].push_back(i);
+    }
+    for (auto &mem : members) {
+      std::vector<DeviceMesh *> dms;
+      std::vector<double> dts;
+      for (int i : mem) {
+        dms.push_back(&meshes[i]->dm);
+        dts.push_back(dt[i]);
+      }
+      Group32 *g = nullptr;
+      std::string gerr;
+      int rc = group32_create(dms, dts, scheme, &g, gerr);
+      if (rc) {
+        for (Group32 *h : groups) group32_destroy(h);
+        return fail(rc, "mesh group: " + gerr);
+      }
+      groups.push_back(g);
+    }
+  }
+  const int nbr = (int)(groups.size() + alone.size());
   hipStream_t cs = nullptr;
-  std::vector<hipStream_t> br(n, nullptr);
-  std::vector<hipEvent_t> join(n, nullptr);
+  std::vector<hipStream_t> br(nbr, nullptr);
+  std::vector<hipEvent_t> join(nbr, nullptr);
   hipEvent_t fork = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1839,27 +1887,38 @@ int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int sc
   bool capturing = false;
   if (chk(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate") &&
       chk(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate")) {
-    for (int i = 0; i < n && rc == FR_OK; ++i)
+    for (int i = 0; i < nbr && rc == FR_OK; ++i)
       if (chk(hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking), "hipStreamCreate"))
         chk(hipEventCreateWithFlags(&join[i], hipEventDisableTiming), "hipEventCreate");
   }
   if (rc == FR_OK && chk(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) {
     capturing = true;
     chk(hipEventRecord(fork, cs), "hipEventRecord");
-    for (int i = 0; i < n && rc == FR_OK; ++i) {
-      if (!chk(hipStreamWaitEvent(br[i], fork, 0), "hipStreamWaitEvent")) break;
-      DeviceMesh &dm = meshes[i]->dm;
-      void *saved = dm.stream;
-      dm.stream = br[i];
-      int r = run_steps(meshes[i], dt[i], scheme, 1, nullptr);
-      dm.stream = saved;
-      if (r) {
-        rc = r;
-        msg = g_err;
-        break;
+    for (int b = 0; b < nbr && rc == FR_OK; ++b) {
+      if (!chk(hipStreamWaitEvent(br[b], fork, 0), "hipStreamWaitEvent")) break;
+      if (b < (int)groups.size()) {
+        std::string gerr;
+        const int r = group32_step(groups[b], br[b], gerr);
+        if (r) {
+          rc = r;
+          msg = gerr;
+          break;
+        }
+      } else {
+        const int i = alone[b - groups.size()];
+        DeviceMesh &dm = meshes[i]->dm;
+        void *saved = dm.stream;
+        dm.stream = br[b];
+        int r = run_steps(meshes[i], dt[i], scheme, 1, nullptr);
+        dm.stream = saved;
+        if (r) {
+          rc = r;
+          msg = g_err;
+          break;
+        }
       }
-      if (!chk(hipEventRecord(join[i], br[i]), "hipEventRecord")) break;
-      chk(hipStreamWaitEvent(cs, join[i], 0), "hipStreamWaitEvent");
+      if (!chk(hipEventRecord(join[b], br[b]), "hipEventRecord")) break;
+      chk(hipStreamWaitEvent(cs, join[b], 0), "hipStreamWaitEvent");
     }
     hipError_t e = hipStreamEndCapture(cs, &graph);
     capturing = false;
@@ -1867,7 +1926,7 @@ int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int sc
   }
   (void)capturing;
   if (rc == FR_OK) chk(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < nbr; ++i) {
     if (join[i]) (void)hipEventDestroy(join[i]);
     if (br[i]) (void)hipStreamDestroy(br[i]);
   }
@@ -1876,11 +1935,13 @@ int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int sc
   if (rc != FR_OK) {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (Group32 *g : groups) group32_destroy(g);
     return fail(rc, "batch capture failed: " + msg);
   }
   fr_batch_s *b = new fr_batch_s();
   b->magic = kBatchMagic;
   b->meshes.assign(meshes, meshes + n);
+  b->groups = groups;
   b->stream = (hipStream_t)hip_stream;
   b->graph = graph;
   b->exec = exec;
@@ -1908,6 +1969,7 @@ int fr_batch_destroy(fr_batch_t b) {
   (void)hipStreamSynchronize(b->stream);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (Group32 *g : b->groups) group32_destroy(g);
   b->magic = 0;
   delete b;
   return FR_OK;

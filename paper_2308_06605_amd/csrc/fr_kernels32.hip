@@ -19,6 +19,8 @@
 // reduced energy E'' = E - H_r rho uses the same wave decomposition as the FP64 solvers.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -814,12 +816,9 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) 
     }                                                            \
   } while (0)
 
-template <int P, bool VISC, int EPBX, int FBS>
-int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
-               double *ms, std::string &err) {
-  using C = Cfg<P>;
-  OpsT<float> ops;
-  OpsT<double> opsd;
+// The kernels' arguments of one mesh: its operator tables in both precisions, the physics in
+// FP32 and the reference state of the split.
+void ops_of(const DeviceMesh &dm, OpsT<float> &ops, OpsT<double> &opsd) {
   for (int i = 0; i < kMaxN * kMaxN; ++i) {
     ops.D[i] = float(dm.ops.D[i]);
     opsd.D[i] = dm.ops.D[i];
@@ -834,7 +833,13 @@ int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, doub
     opsd.gcL[i] = dm.ops.gcL[i];
     opsd.gcR[i] = dm.ops.gcR[i];
   }
-  Phys<float> ph{float(dm.phys.gamma), float(dm.phys.gamma - 1.0), float(dm.phys.mu), float(dm.phys.kappa)};
+}
+
+Phys<float> phys32_of(const DeviceMesh &dm) {
+  return Phys<float>{float(dm.phys.gamma), float(dm.phys.gamma - 1.0), float(dm.phys.mu), float(dm.phys.kappa)};
+}
+
+Ref32 ref32_of(const DeviceMesh &dm) {
   Ref32 ref;
   ref.rho_d = dm.ref_rho;
   ref.E_d = dm.ref_p / (dm.phys.gamma - 1.0);
@@ -843,6 +848,85 @@ int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, doub
   ref.E = float(ref.E_d);
   ref.H = float(ref.H_d);
   ref.p = float(dm.ref_p);
+  return ref;
+}
+
+// ------------------------------------------------------------------------------------------
+// Many meshes in one launch (batches). A group holds meshes of one degree; each kernel launch
+// covers every mesh of the group with one block per work item: an element block (pre-pass,
+// volume) or a face block (face kernel) of some mesh. Block b finds its mesh m in the table's
+// prefix sums of item counts, first[m] <= b < first[m + 1], and runs the single-mesh kernel's
+// body for block b - first[m] with that mesh's arguments from a device table, so every mesh's
+// results equal what the single-mesh kernels give it. The hardware's block dispatcher balances
+// the items over the CUs; a block does exactly one item, as in the single-mesh kernels, so the
+// bodies compile to the same register budget.
+// ------------------------------------------------------------------------------------------
+struct Slice32 {
+  const double *X[10];  // the state stage s is evaluated on
+  StageArgs st[10];     // stage s's register update (dt of this mesh)
+  double *out0, *reg1, *reg2;
+  const double *geo;
+  const float *geo32;
+  const FaceRef *fref;
+  float *face32;
+  double *facem;
+  const double *fgeo;
+  const FaceRec *ftab;
+  float *fout32;
+  double *foutm;
+  int64_t E, F;
+  Phys<float> ph;
+  Ref32 ref;
+  int flux;
+  float tw_gm1, cw;
+};
+
+// The mesh of work item `item` (uniform over the block: the table entry is read by scalar loads).
+__device__ __forceinline__ int slice_of(const int64_t *first, int nm, int64_t item) {
+  int m = 0;
+  while (m + 1 < nm && first[m + 1] <= item) ++m;
+  return m;
+}
+
+template <int P, bool VISC, int EPBX>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) void k_prepass32_multi(const Slice32 *__restrict__ tab,
+                                                                       const int64_t *__restrict__ first, int nm,
+                                                                       int s, OpsT<float> ops, OpsT<double> opsd) {
+  const int m = slice_of(first, nm, blockIdx.x);
+  const Slice32 &sl = tab[m];
+  prepass32_body<P, VISC, EPBX>(blockIdx.x - (unsigned)first[m], sl.X[s], sl.geo32, sl.face32, sl.facem, sl.E, ops,
+                                opsd, sl.ref);
+}
+
+template <int P, bool VISC, int FBS>
+__global__ __launch_bounds__(FBS) void k_face32_multi(const Slice32 *__restrict__ tab,
+                                                      const int64_t *__restrict__ first, int nm) {
+  const int m = slice_of(first, nm, blockIdx.x);
+  const Slice32 &sl = tab[m];
+  face32_body<P, VISC, FBS>(blockIdx.x - (unsigned)first[m], sl.face32, sl.facem, sl.fgeo, sl.ftab, sl.F, sl.ph,
+                            sl.ref, sl.flux, sl.tw_gm1, sl.cw, sl.fout32, sl.foutm);
+}
+
+template <int P, bool VISC, int EPBX, bool PRE>
+__global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME32(P)) void k_volume32_multi(
+    const Slice32 *__restrict__ tab, const int64_t *__restrict__ first, int nm, int s, OpsT<float> ops,
+    OpsT<double> opsd) {
+  const int m = slice_of(first, nm, blockIdx.x);
+  const Slice32 &sl = tab[m];
+  volume32_body<P, VISC, EPBX, PRE>(blockIdx.x - (unsigned)first[m], sl.X[s], sl.geo, sl.fref, sl.fout32, sl.foutm,
+                                    sl.E, ops, opsd, sl.ph, sl.ref, sl.st[s], sl.out0, sl.reg1, sl.reg2,
+                                    PRE ? sl.face32 : nullptr, PRE ? sl.facem : nullptr, PRE ? sl.geo32 : nullptr);
+}
+
+template <int P, bool VISC, int EPBX, int FBS>
+int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, double *reg1, double *reg2,
+               double *ms, std::string &err) {
+  using C = Cfg<P>;
+  OpsT<float> ops;
+  OpsT<double> opsd;
+  ops_of(dm, ops, opsd);
+  const Phys<float> ph = phys32_of(dm);
+  const Ref32 ref = ref32_of(dm);
   const double tw_gm1 = dm.wall_T / (dm.phys.gamma - 1.0);
   const float cw = float(ref.rho_d * tw_gm1 - ref.E_d);
   const int64_t blocks = (dm.E + EPBX - 1) / EPBX;
@@ -935,6 +1019,81 @@ int launch32_p(DeviceMesh &dm, const double *X, StageArgs st, double *o, double 
   }
 }
 
+// A group's device tables and item counts (see Slice32).
+struct Group32Impl {
+  int p = 0, ns = 0, epb = 0, fbs = 0, nm = 0;
+  bool fuse = true;
+  Slice32 *tab = nullptr;
+  int64_t *first_e = nullptr, *first_f = nullptr;
+  OpsT<float> ops;
+  OpsT<double> opsd;
+  int64_t items_e = 0, items_f = 0;
+};
+
+// setup: check that the item counts fit a launch; otherwise enqueue one RK step of every mesh of
+// the group
+template <int P, int EPB, int FBS>
+int group32_t(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
+  constexpr int TB = EPB * Cfg<P>::NS;
+  if (setup) {
+    if (g.items_e * TB > (int64_t)UINT32_MAX || g.items_f * FBS > (int64_t)UINT32_MAX) {
+      err = "a mesh group's launch exceeds 2^32 threads";
+      return -1;
+    }
+    return 0;
+  }
+  const dim3 ge((unsigned)g.items_e), gf((unsigned)g.items_f);
+  for (int st = 0; st < g.ns; ++st) {
+    if (st == 0 || !g.fuse) {
+      hipLaunchKernelGGL((k_prepass32_multi<P, true, EPB>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st, g.ops,
+                         g.opsd);
+      HIPCHK32(hipGetLastError());
+    }
+    hipLaunchKernelGGL((k_face32_multi<P, true, FBS>), gf, dim3(FBS), 0, s, g.tab, g.first_f, g.nm);
+    HIPCHK32(hipGetLastError());
+    if (g.fuse && st < g.ns - 1)
+      hipLaunchKernelGGL((k_volume32_multi<P, true, EPB, true>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st,
+                         g.ops, g.opsd);
+    else
+      hipLaunchKernelGGL((k_volume32_multi<P, true, EPB, false>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st,
+                         g.ops, g.opsd);
+    HIPCHK32(hipGetLastError());
+  }
+  return 0;
+}
+
+template <int P>
+int group32_tiles(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
+  constexpr int E0 = Cfg<P>::EPB, E1 = E0 > 1 ? E0 / 2 : 1;
+  if (g.epb == 0) {
+    if (g.fbs == 0) return group32_t<P, E0, 256>(g, s, setup, err);
+    if (g.fbs == 1) return group32_t<P, E0, 128>(g, s, setup, err);
+    return group32_t<P, E0, 64>(g, s, setup, err);
+  }
+  if (g.fbs == 0) return group32_t<P, E1, 256>(g, s, setup, err);
+  if (g.fbs == 1) return group32_t<P, E1, 128>(g, s, setup, err);
+  return group32_t<P, E1, 64>(g, s, setup, err);
+}
+
+int group32_dispatch(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
+  switch (g.p) {
+    case 1: return group32_tiles<1>(g, s, setup, err);
+    case 2: return group32_tiles<2>(g, s, setup, err);
+    case 3: return group32_tiles<3>(g, s, setup, err);
+    case 4: return group32_tiles<4>(g, s, setup, err);
+    case 5: return group32_tiles<5>(g, s, setup, err);
+    case 6: return group32_tiles<6>(g, s, setup, err);
+    case 7: return group32_tiles<7>(g, s, setup, err);
+    default: err = "multi-mesh groups take p = 1..7"; return -5;
+  }
+}
+
+void free_group32(Group32Impl *g) {
+  for (void *b : {(void *)g->tab, (void *)g->first_e, (void *)g->first_f})
+    if (b) (void)hipFree(b);
+  delete g;
+}
+
 }  // namespace
 
 namespace frk {
@@ -945,5 +1104,109 @@ namespace frk {
 int launch_stage32(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
                    std::string &err) {
   return dm.viscous ? launch32_p<true>(dm, X, st, o, r1, r2, ms, err) : launch32_p<false>(dm, X, st, o, r1, r2, ms, err);
+}
+
+bool group32_eligible(const DeviceMesh &dm) {
+  return dm.prec == 1 && dm.viscous && !dm.ldg && dm.sgs == 0 && dm.p >= 1 && dm.p <= kMaxP;
+}
+
+int group32_create(const std::vector<DeviceMesh *> &meshes, const std::vector<double> &dt, int scheme, Group32 **out,
+                   std::string &err) {
+  *out = nullptr;
+  const int nm = (int)meshes.size();
+  if (nm < 1) {
+    err = "empty group";
+    return -1;
+  }
+  Group32Impl *g = new Group32Impl();
+  g->p = meshes[0]->p;
+  g->nm = nm;
+  g->ns = n_stages(scheme);
+  g->fuse = meshes[0]->fuse;
+  ops_of(*meshes[0], g->ops, g->opsd);
+  // the tiles of the group's meshes (one setting per group)
+  g->epb = meshes[0]->tile_epb;
+  g->fbs = meshes[0]->tile_fbs;
+  const int NS = meshes[0]->Ns, NFP = meshes[0]->Nfp;
+  const int E0 = (256 / NS) > 64 ? 64 : ((256 / NS) > 0 ? (256 / NS) : 1);
+  const int epb = g->epb == 0 ? E0 : (E0 > 1 ? E0 / 2 : 1);
+  const int fbs = g->fbs == 0 ? 256 : (g->fbs == 1 ? 128 : 64);
+  std::vector<Slice32> tab(nm);
+  std::vector<int64_t> fe(nm + 1, 0), ff(nm + 1, 0);
+  for (int i = 0; i < nm; ++i) {
+    DeviceMesh &dm = *meshes[i];
+    if (dm.p != g->p || !group32_eligible(dm) || dm.fuse != g->fuse || dm.tile_epb != g->epb || dm.tile_fbs != g->fbs) {
+      free_group32(g);
+      err = "meshes of a group need one degree, the viscous FP32 form without closure or LDG, one fusion setting "
+            "and one tile setting";
+      return -1;
+    }
+    Slice32 &sl = tab[i];
+    std::memset(&sl, 0, sizeof sl);
+    for (int st = 0; st < g->ns; ++st) {
+      const double *X;
+      double *o, *r1, *r2;
+      stage_setup(dm, scheme, st, dt[i], sl.st[st], &X, &o, &r1, &r2);
+      sl.st[st].force = dm.has_force ? 1 : 0;
+      for (int k = 0; k < 3; ++k) sl.st[st].g[k] = dm.force[k];
+      sl.X[st] = X;
+      sl.out0 = o;
+      sl.reg1 = r1;
+      sl.reg2 = r2;
+    }
+    sl.geo = (const double *)dm.geo;
+    sl.geo32 = (const float *)dm.geo32;
+    sl.fref = dm.fref;
+    sl.face32 = (float *)dm.face32;
+    sl.facem = (double *)dm.facem;
+    sl.fgeo = (const double *)dm.fgeo;
+    sl.ftab = dm.ftab;
+    sl.fout32 = (float *)dm.fout32;
+    sl.foutm = (double *)dm.foutm;
+    sl.E = dm.E;
+    sl.F = dm.F;
+    sl.ph = phys32_of(dm);
+    sl.ref = ref32_of(dm);
+    sl.flux = dm.flux;
+    const double tw_gm1 = dm.wall_T / (dm.phys.gamma - 1.0);
+    sl.tw_gm1 = float(tw_gm1);
+    sl.cw = float(sl.ref.rho_d * tw_gm1 - sl.ref.E_d);
+    fe[i + 1] = fe[i] + (dm.E + epb - 1) / epb;
+    ff[i + 1] = ff[i] + (dm.F * NFP + fbs - 1) / fbs;
+  }
+  g->items_e = fe[nm];
+  g->items_f = ff[nm];
+  if (hipMalloc(&g->tab, nm * sizeof(Slice32)) != hipSuccess ||
+      hipMalloc(&g->first_e, (nm + 1) * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&g->first_f, (nm + 1) * sizeof(int64_t)) != hipSuccess ||
+      hipMemcpy(g->tab, tab.data(), nm * sizeof(Slice32), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->first_e, fe.data(), (nm + 1) * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->first_f, ff.data(), (nm + 1) * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+    free_group32(g);
+    err = "device tables of a mesh group";
+    return -4;
+  }
+  int rc = group32_dispatch(*g, nullptr, true, err);
+  if (rc) {
+    free_group32(g);
+    return rc;
+  }
+  *out = reinterpret_cast<Group32 *>(g);
+  return 0;
+}
+
+int group32_step(Group32 *g, void *stream, std::string &err) {
+  return group32_dispatch(*reinterpret_cast<Group32Impl *>(g), (hipStream_t)stream, false, err);
+}
+
+void group32_destroy(Group32 *g) {
+  if (g) free_group32(reinterpret_cast<Group32Impl *>(g));
+}
+
+int group32_items(const Group32 *g, int64_t *elem_items, int64_t *face_items) {
+  const Group32Impl *gi = reinterpret_cast<const Group32Impl *>(g);
+  *elem_items = gi->items_e;
+  *face_items = gi->items_f;
+  return 0;
 }
 }  // namespace frk

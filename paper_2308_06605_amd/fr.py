@@ -95,6 +95,7 @@ def load():
     L.fr_part_residual.argtypes = [P, P, i32]
     L.fr_part_rk_step.argtypes = [P, f64, i32, i32]
     L.fr_batch_create.argtypes = [P, ctypes.c_int32, P, i32, P, ctypes.POINTER(P)]
+    L.fr_batch_create_ex.argtypes = [P, ctypes.c_int32, P, i32, P, ctypes.c_int32, ctypes.POINTER(P)]
     L.fr_batch_step.argtypes = [P, i32]
     L.fr_batch_set_stream.argtypes = [P, P]
     L.fr_batch_destroy.argtypes = [P]
@@ -119,7 +120,7 @@ def load():
     for name in ("fr_mesh_create", "fr_mesh_destroy", "fr_set_stream", "fr_sol_coords", "fr_set_state",
                  "fr_get_state", "fr_residual", "fr_rk_step", "fr_mesh_info", "fr_profile_stages",
                  "fr_mesh_geometry_host", "fr_basis_host", "fr_rk_coefficients", "fr_kinetic_energy", "fr_sgs_n_features", "fr_set_body_force",
-                 "fr_batch_create", "fr_batch_step", "fr_batch_set_stream", "fr_batch_destroy",
+                 "fr_batch_create", "fr_batch_create_ex", "fr_batch_step", "fr_batch_set_stream", "fr_batch_destroy",
                  "fr_set_tiles", "fr_get_tiles", "fr_autotune", "fr_set_fusion", "fr_get_fusion",
                  "fr_sgs_features", "fr_set_eddy_viscosity", "fr_set_sgs_model", "fr_get_eddy_viscosity",
                  "fr_mlp_create", "fr_mlp_destroy", "fr_mlp_set_stream", "fr_mlp_set_params",
@@ -633,10 +634,15 @@ class PartitionGroup:
             pass
 
 
-class Batch:
-    """Meshes advanced together by one captured HIP graph per RK step (fr_batch_*)."""
+BATCH_MULTI = 1  # FR_BATCH_MULTI
 
-    def __init__(self, meshes, dts, scheme: str = "lsrk45", stream=None):
+
+class Batch:
+    """Meshes advanced together by one captured HIP graph per RK step (fr_batch_*). multi=True
+    (the default) steps the viscous FP32-form meshes with the multi-mesh kernels, one launch per
+    kernel, stage and degree; multi=False gives every mesh a graph branch of its own."""
+
+    def __init__(self, meshes, dts, scheme: str = "lsrk45", stream=None, multi: bool = True):
         L = load()
         self.meshes = list(meshes)  # kept alive with the batch
         n = len(self.meshes)
@@ -644,8 +650,8 @@ class Batch:
         dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dts, dtype=np.float64), (n,)))
         self._stream = _current_stream() if stream is None else ctypes.c_void_p(stream)
         h = ctypes.c_void_p()
-        _check(L.fr_batch_create(ctypes.cast(handles, ctypes.c_void_p), n, dt.ctypes.data, SCHEME[scheme],
-                                 self._stream, ctypes.byref(h)))
+        _check(L.fr_batch_create_ex(ctypes.cast(handles, ctypes.c_void_p), n, dt.ctypes.data, SCHEME[scheme],
+                                    self._stream, BATCH_MULTI if multi else 0, ctypes.byref(h)))
         self.h = h
 
     def step(self, n_steps: int = 1):
