@@ -7,11 +7,15 @@ network, against the filtered 32^3 p=7 run stored with the model (made by `closu
 What it shows: at this resolution the Roe/BR2 scheme's own numerical dissipation already
 exceeds the filtered run's during the transition (t = 3.5 to 5.5), so the learned eddy viscosity
 (about 0.1 mu on average) adds dissipation the coarse run does not need: its kinetic-energy
-error is larger than implicit LES's (error ratio implicit/learned about 0.75 at t <= 7; < 1 means
-no gain). The test re-derives that comparison on the GPU up to t = 4.5 and checks
+error is larger than implicit LES's. The gain is the error ratio implicit / learned (> 1 would
+be a gain): 0.543 at t <= 4.5 and 0.753 at t <= 7 in the stored evaluation. The test re-derives
+the comparison on the GPU up to t = 4.5 and checks
 * the network acts (nu_t > 0) and dissipates (less kinetic energy than implicit LES),
 * both runs track the filtered reference closely (relative error below 1 %),
-* the sign of the gain: the learned closure does not beat implicit LES here.
+* the measured gain: 0.543 (a loss), within 1 % of the stored evaluation's.
+The energies are also compared with the stored evaluation's: that is a regression check of the
+deterministic kernels, not parity (the closure path's parity against the oracle is
+test_gpu_sgs.py's RK4 step with per-stage nu_t).
 """
 import os
 
@@ -43,7 +47,9 @@ def test_learned_closure_against_implicit_les():
     assert np.all(nu > 0)
     assert np.all(ek_l[1:] < ek_i[1:])
     assert e_i < 0.01 and e_l < 0.01
-    # the same runs as the stored evaluation (deterministic kernels): identical energies
+    # regression against the stored evaluation (deterministic kernels): identical energies
     ek_stored = d["eval_ek"][:, keep]
     assert np.allclose(ek_i, ek_stored[0], rtol=1e-10) and np.allclose(ek_l, ek_stored[1], rtol=1e-10)
-    assert e_i < e_l  # no gain at this resolution (see the module docstring)
+    # the gain and its sign: 0.543, a loss at this resolution (see the module docstring)
+    gain = e_i / e_l
+    assert abs(gain - 0.543) < 0.01 * 0.543, gain
