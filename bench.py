@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_2308_06605_amd.profiling import algorithmic_bytes  # noqa: E402 (the byte accounting)
+
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 STAGES = {"lsrk45": 5, "rk4": 4}
 KERNEL_NAMES = {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume", "volume_pre": "k_volume_pre"}
@@ -36,47 +38,6 @@ def kernel_name(key: str, prec: str) -> str:
     if prec != "fp32":
         return KERNEL_NAMES[key]
     return "k_volume32_pre" if key == "volume_pre" else KERNEL_NAMES[key] + "32"
-
-
-def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
-    """HBM bytes per element per stage that each kernel must move (every input read once,
-    every output written once); the state and RK registers are always FP64.
-
-    pre-pass : read U (5 Ns) and volume geometry (10 Ns); write own face data (20 Nf)
-    face     : per face point read both sides' face data (2 x 20) and the face geometry (4),
-               write the jump and common flux (10); per element that is 3 Nfp points
-    volume   : read U (5 Ns), the volume geometry (10 Ns), its faces' jumps and fluxes (10 Nf)
-               and the RK register (5 Ns); write the register (5 Ns) and U (5 Ns): 30 Ns + 10 Nf
-               (an LSRK45 run's first stage reads no register: 25 Ns)
-    volume_pre : the volume kernel that also runs the next stage's pre-pass on the state it
-               stores: the volume kernel's bytes plus the pre-pass's writes (FP64 20 Nf doubles;
-               FP32 form 20 Nf floats + 3 Nf doubles); its reads of U and the geometry are the
-               volume kernel's own
-    In the FP64 path a stage is face + volume_pre, 8 (30 Ns + 57 Nf) per element: 924 B/DOF at
-    p = 3. `stage_min` is the two-pass minimum of a stage that reads its inputs in both passes:
-    FP64 8 (45 Ns + 44 Nf); FP32 form (FP64 state, FP32 geometry and face data)
-    8 * 25 Ns + 4 (20 Ns + 44 Nf). The roofline of the whole stage is taken on it.
-    """
-    n = p + 1
-    Ns, Nfp = n ** 3, n * n
-    Nf = 6 * Nfp
-    nv = 20 if viscous else 5
-    if prec == "fp64":
-        k1 = 8 * 5 * Ns + 8 * (10 * Ns + nv * Nf)
-        k2 = 8 * 3 * Nfp * (2 * nv + 4 + 10)
-        k3 = 8 * 20 * Ns + 8 * (10 * Ns + 10 * Nf)
-        stage_min = 8 * (45 * Ns + 44 * Nf)
-    else:
-        # FP32 form: FP32 geometry copy for the pre-pass, face data as 20 floats + 3 doubles,
-        # face results as 9 floats + 1 double; the volume kernel reads FP64 geometry (mass)
-        k1 = 8 * 5 * Ns + 4 * 10 * Ns + (4 * nv + 8 * 3) * Nf
-        k2 = 3 * Nfp * (2 * (4 * nv + 8 * 3) + 8 * 4 + 4 * 9 + 8)
-        k3 = 8 * 20 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
-        stage_min = 8 * 25 * Ns + 4 * (20 * Ns + 44 * Nf)
-    out = {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
-    # the volume kernel with the next stage's pre-pass adds the pre-pass's writes
-    out["volume_pre"] = k3 + (8 * nv * Nf if prec == "fp64" else (4 * nv + 8 * 3) * Nf)
-    return out
 
 
 def make_workload(n: int, p: int, curved: bool):

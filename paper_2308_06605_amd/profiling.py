@@ -6,6 +6,11 @@ FETCH_SIZE and one WRITE_SIZE):
   python -m paper_2308_06605_amd.profiling --fetch <dir>/run_counter_collection.csv \\
       --write <dir>/run_counter_collection.csv --calib-bytes 268435456 --out <summary.json>
 
+The stage summary of a workload (a `rocprofv3 --kernel-trace --stats` run and the traffic JSON):
+
+  python -m paper_2308_06605_amd.profiling stage --stats <dir>/run_kernel_stats.csv \\
+      --traffic <traffic.json> --n 64 --p 3 --prec fp64 --tiles 0 2 --fuse 1 --command "<cmd>" --out <md>
+
 Other counters (any number of `--pmc` passes over the same command):
 
   python -m paper_2308_06605_amd.profiling counters <csv> [<csv> ...] --out <summary.md>
@@ -34,6 +39,47 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # and launchers, while the entry points after it do not change what a kernel does
 KERNEL_SOURCES = {"fp64": ("fr_kernels.hip", "fr_device.h", "fr_internal.h"),
                   "fp32": ("fr_kernels32.hip", "fr_device.h", "fr_internal.h")}
+
+
+def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
+    """HBM bytes per element per stage that each kernel must move (every input read once,
+    every output written once); the state and RK registers are always FP64.
+
+    pre-pass : read U (5 Ns) and volume geometry (10 Ns); write own face data (20 Nf)
+    face     : per face point read both sides' face data (2 x 20) and the face geometry (4),
+               write the jump and common flux (10); per element that is 3 Nfp points
+    volume   : read U (5 Ns), the volume geometry (10 Ns), its faces' jumps and fluxes (10 Nf)
+               and the RK register (5 Ns); write the register (5 Ns) and U (5 Ns): 30 Ns + 10 Nf
+               (an LSRK45 run's first stage reads no register: 25 Ns)
+    volume_pre : the volume kernel that also runs the next stage's pre-pass on the state it
+               stores: the volume kernel's bytes plus the pre-pass's writes (FP64 20 Nf doubles;
+               FP32 form 20 Nf floats + 3 Nf doubles); its reads of U and the geometry are the
+               volume kernel's own
+    In the FP64 path a stage is face + volume_pre, 8 (30 Ns + 57 Nf) per element: 924 B/DOF at
+    p = 3. `stage_min` is the two-pass minimum of a stage that reads its inputs in both passes:
+    FP64 8 (45 Ns + 44 Nf); FP32 form (FP64 state, FP32 geometry and face data)
+    8 * 25 Ns + 4 (20 Ns + 44 Nf). The roofline of the whole stage is taken on it.
+    """
+    n = p + 1
+    Ns, Nfp = n ** 3, n * n
+    Nf = 6 * Nfp
+    nv = 20 if viscous else 5
+    if prec == "fp64":
+        k1 = 8 * 5 * Ns + 8 * (10 * Ns + nv * Nf)
+        k2 = 8 * 3 * Nfp * (2 * nv + 4 + 10)
+        k3 = 8 * 20 * Ns + 8 * (10 * Ns + 10 * Nf)
+        stage_min = 8 * (45 * Ns + 44 * Nf)
+    else:
+        # FP32 form: FP32 geometry copy for the pre-pass, face data as 20 floats + 3 doubles,
+        # face results as 9 floats + 1 double; the volume kernel reads FP64 geometry (mass)
+        k1 = 8 * 5 * Ns + 4 * 10 * Ns + (4 * nv + 8 * 3) * Nf
+        k2 = 3 * Nfp * (2 * (4 * nv + 8 * 3) + 8 * 4 + 4 * 9 + 8)
+        k3 = 8 * 20 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
+        stage_min = 8 * 25 * Ns + 4 * (20 * Ns + 44 * Nf)
+    out = {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
+    # the volume kernel with the next stage's pre-pass adds the pre-pass's writes
+    out["volume_pre"] = k3 + (8 * nv * Nf if prec == "fp64" else (4 * nv + 8 * 3) * Nf)
+    return out
 
 
 def kernel_source_hash(prec: str = "fp64") -> str:
@@ -147,9 +193,82 @@ def counters_markdown(paths, title: str, command: str) -> str:
     return "\n".join(lines)
 
 
+def kernel_stats(path: str) -> dict:
+    """{short kernel name: (calls, avg ms, min ms, max ms)} from rocprofv3's kernel_stats.csv."""
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            k = short_name(r["Name"])
+            if not k.startswith("k_"):
+                continue
+            out[k] = (int(r["Calls"]), float(r["AverageNs"]) * 1e-6, float(r["MinNs"]) * 1e-6,
+                      float(r["MaxNs"]) * 1e-6)
+    return out
+
+
+def stage_markdown(stats_csv: str, traffic_json: str, n: int, p: int, prec: str, tiles, fuse: bool,
+                   trace_command: str) -> str:
+    """The stage summary of one workload: per kernel the profiler's launch times, the algorithmic
+    bytes per launch (algorithmic_bytes times the element count) and the counters' HBM bytes."""
+    st = kernel_stats(stats_csv)
+    with open(traffic_json) as f:
+        tr = json.load(f)
+    E = n ** 3
+    ab = algorithmic_bytes(p, prec)
+    kinds = {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume", "volume_pre": "k_volume_pre"}
+    if prec == "fp32":
+        kinds = {k: ("k_volume32_pre" if k == "volume_pre" else v + "32") for k, v in kinds.items()}
+    epb = "256/Ns" if tiles[0] == 0 else "half of 256/Ns"
+    fbs = (256, 128, 64)[tiles[1]]
+    src = kernel_source_hash(prec)
+    lines = [f"# Stage kernels, {n}^3 p={p} curved TGV (Roe+BR2, LSRK45), {prec.upper()}", "",
+             f"Kernel trace: `{trace_command}` (tiles (elements per block, face block) = ({epb}, {fbs}), "
+             f"fused pre-pass {'on' if fuse else 'off'}).", "",
+             f"Traffic: `{tr.get('command', '')}`; FETCH_SIZE scaled by {tr['fetch_scale']:.4f}, WRITE_SIZE by "
+             f"{tr['write_scale']:.4f} (the factors that make a {tr['calibration_copy_bytes'] >> 20} MiB device copy "
+             f"read and write that many bytes). Counters taken on kernel sources {tr['kernel_source_hash']}; "
+             f"the trace on {src}" + (" (same)." if src == tr["kernel_source_hash"] else " (the counters are stale)."),
+             "", "| kernel | calls | avg ms | min ms | max ms | algorithmic GB/launch | measured HBM GB/launch "
+             "(read + write) | algorithmic GB/s at avg | measured GB/s at avg |", "|---|---|---|---|---|---|---|---|---|"]
+    for kind, name in kinds.items():
+        if name not in st:
+            continue
+        calls, avg, mn, mx = st[name]
+        alg = ab[kind] * E / 1e9
+        k = tr["kernels"].get(name)
+        rd, wr = (k["fetch_bytes"] / 1e9, k["write_bytes"] / 1e9) if k else (float("nan"), float("nan"))
+        lines.append(f"| {name} | {calls} | {avg:.4f} | {mn:.4f} | {mx:.4f} | {alg:.3f} | {rd:.3f} + {wr:.3f} | "
+                     f"{alg / avg * 1e3:.0f} | {(rd + wr) / avg * 1e3:.0f} |")
+    face, vol = kinds["face"], kinds["volume_pre"]
+    if face in st and vol in st:
+        t = st[face][1] + st[vol][1]
+        smin = ab["stage_min"] * E
+        lines += ["", f"Stage ({face} + {vol}): {t:.4f} ms, {n ** 3 * (p + 1) ** 3 / (t * 1e-3):.4g} DOF-updates/s; "
+                  f"two-pass minimum {smin / 1e9:.3f} GB per stage, {smin / (t * 1e-3) / 1e9:.0f} GB/s, "
+                  f"{smin / (t * 1e-3) / 8e12:.3f} of 8 TB/s."]
+    return "\n".join(lines) + "\n"
+
+
 def main():
     import sys
 
+    if len(sys.argv) > 1 and sys.argv[1] == "stage":
+        ap = argparse.ArgumentParser(prog="profiling stage")
+        ap.add_argument("--stats", required=True, help="rocprofv3 --stats kernel_stats.csv")
+        ap.add_argument("--traffic", required=True, help="the traffic summary JSON of the same workload")
+        ap.add_argument("--n", type=int, required=True)
+        ap.add_argument("--p", type=int, required=True)
+        ap.add_argument("--prec", choices=("fp64", "fp32"), required=True)
+        ap.add_argument("--tiles", type=int, nargs=2, required=True)
+        ap.add_argument("--fuse", type=int, choices=(0, 1), required=True)
+        ap.add_argument("--command", required=True, help="the kernel-trace command, recorded")
+        ap.add_argument("--out", required=True)
+        a = ap.parse_args(sys.argv[2:])
+        text = stage_markdown(a.stats, a.traffic, a.n, a.p, a.prec, a.tiles, bool(a.fuse), a.command)
+        with open(a.out, "w") as f:
+            f.write(text)
+        print(text)
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "counters":
         ap = argparse.ArgumentParser(prog="profiling counters")
         ap.add_argument("csv", nargs="+")
