@@ -20,7 +20,7 @@ Three ways to run the same steps are timed on the same meshes and state:
 Throughput is the total DOF-updates per second per RK stage; the roofline fraction is the
 meshes' summed two-pass minimum bytes per stage over the stage time at 8 TB/s.
 
-  python -m paper_2308_06605_amd.batched [--n-mesh 48] [--steps 10] [--seed 0]
+  python -m paper_2308_06605_amd.batched [--n-mesh 48] [--steps 10] [--seed 0] [--sizes 8 40]
 """
 from __future__ import annotations
 
@@ -38,9 +38,9 @@ GAMMA = 1.4
 MU = 1e-4
 
 
-def workload(n_mesh: int, seed: int):
+def workload(n_mesh: int, seed: int, n_min: int = 8, n_max: int = 40):
     rng = np.random.default_rng(seed)
-    N = np.exp(rng.uniform(math.log(8 ** 3), math.log(40 ** 3), n_mesh))
+    N = np.exp(rng.uniform(math.log(n_min ** 3), math.log(n_max ** 3), n_mesh))
     n = np.maximum(3, np.rint(np.cbrt(N)).astype(int))
     p = rng.integers(2, 6, n_mesh)
     mach = rng.uniform(0.2, 0.5, n_mesh)
@@ -71,13 +71,13 @@ def build(fr, spec, walls=True, prec="fp32"):
     return g, U
 
 
-def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune=True):
+def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune=True, sizes=(8, 40)):
     import torch
 
     from . import fr
 
     fr.load()
-    specs = workload(n_mesh, seed)
+    specs = workload(n_mesh, seed, *sizes)
     t0 = time.time()
     meshes, states, dts = [], [], []
     for s in specs:
@@ -144,7 +144,7 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune
         rec["roofline_frac"] = stage_bytes / (rec["ms_per_step"] / stages * 1e-3) / 8e12
     geo = "channel meshes (isothermal walls in y)" if walls else "periodic box meshes"
     out = {
-        "workload": f"{n_mesh} {geo}, log-uniform 8^3..40^3 elements, p in 2..5, Mach 0.2-0.5, "
+        "workload": f"{n_mesh} {geo}, log-uniform {sizes[0]}^3..{sizes[1]}^3 elements, p in 2..5, Mach 0.2-0.5, "
                     f"Roe+BR2 mu={MU}, {'FP32 form' if prec == 'fp32' else 'FP64'}, LSRK45, "
                     f"{'autotuned' if autotune else 'default'} tiles, seed {seed}",
         "n_mesh": n_mesh, "dof": int(dof), "elements": int(sum(g.E for g in meshes)),
@@ -174,10 +174,12 @@ def main(argv=None):
     ap.add_argument("--periodic", action="store_true", help="fully periodic boxes instead of channels")
     ap.add_argument("--fp64", action="store_true", help="the FP64 kernels instead of the FP32 form")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
+    ap.add_argument("--sizes", type=int, nargs=2, default=(8, 40), metavar=("MIN", "MAX"),
+                    help="elements per direction: the meshes' element counts are log-uniform in MIN^3..MAX^3")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     res = run(a.n_mesh, a.steps, a.warmup, a.seed, not a.periodic, "fp64" if a.fp64 else "fp32",
-              not a.no_autotune)
+              not a.no_autotune, tuple(a.sizes))
     line = {k: v for k, v in res.items() if k != "meshes"}
     print(json.dumps(line), flush=True)
     if a.out:
