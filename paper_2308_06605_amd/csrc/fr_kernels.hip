@@ -22,6 +22,7 @@
 // computes the per-element features (k_sgs_features) and the network's eddy viscosity.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdint>
@@ -1852,6 +1853,10 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
       members[k].push_back(i);
     }
     for (auto &mem : members) {
+      // largest meshes first: their blocks are dispatched first and the small meshes' blocks
+      // fill the end of each launch
+      std::stable_sort(mem.begin(), mem.end(),
+                       [&](int a, int b) { return meshes[a]->dm.E > meshes[b]->dm.E; });
       std::vector<DeviceMesh *> dms;
       std::vector<double> dts;
       for (int i : mem) {

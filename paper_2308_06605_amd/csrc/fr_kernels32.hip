@@ -881,11 +881,18 @@ struct Slice32 {
   float tw_gm1, cw;
 };
 
-// The mesh of work item `item` (uniform over the block: the table entry is read by scalar loads).
+// The mesh of work item `item`: the largest m with first[m] <= item (first[0] = 0), by bisection
+// (uniform over the block: the table is read by scalar loads).
 __device__ __forceinline__ int slice_of(const int64_t *first, int nm, int64_t item) {
-  int m = 0;
-  while (m + 1 < nm && first[m + 1] <= item) ++m;
-  return m;
+  int lo = 0, hi = nm - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 template <int P, bool VISC, int EPBX>
