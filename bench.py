@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from paper_2308_06605_amd.profiling import algorithmic_bytes  # noqa: E402 (the byte accounting)
+from paper_2308_06605_amd.profiling import algorithmic_bytes, tile_elements  # noqa: E402 (the byte accounting)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 STAGES = {"lsrk45": 5, "rk4": 4}
@@ -187,7 +187,7 @@ def run_config(fr, inputs, n, p, prec, args, mu, curved=True):
                      f"{'FP64' if prec == 'fp64' else 'FP32 operators/fluxes, FP64 state and mass'}"),
         "n": n, "n_elem": E, "dof": dof, "p": p, "prec": prec,
         "value": dof * stages / (ms_step * 1e-3), "ms_per_step": ms_step, "stage_ms": stage_ms,
-        "tiles": {"elements_per_block": ("256/Ns", "half of 256/Ns")[tiles[0]],
+        "tiles": {"elements_per_block": tile_elements(p, tiles[0]), "epb_choice": int(tiles[0]),
                   "face_block": (256, 128, 64)[tiles[1]], "fused_prepass": fused,
                   "autotune_ms_per_stage": None if tile_ms is None else [float(x) for x in tile_ms]},
         "roofline": {"bound": "hbm", "achieved": stage_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -140,7 +140,8 @@ int fr_get_state(fr_mesh_t m, double *U, int on_device);
 
 /* Tile shapes of the stage kernels (both precisions), chosen by the autotuner or by the caller:
  *   epb  elements per block of the element kernels (pre-pass, volume): 0 = 256/N_s (at least
- *        one), 1 = half of that (at least one);
+ *        one, at most 64), 1 = half of that, or, where that is one element whose N_s points
+ *        leave lanes of the last wave idle (p = 5, 6), two elements;
  *   fbs  threads per block of the face kernel: 0 = 256, 1 = 128, 2 = 64.
  * Results are bitwise independent of the tiles (every thread does the same arithmetic). A batch
  * captures the tiles in force at its creation. */

@@ -210,6 +210,10 @@ struct Cfg {
   static constexpr int NF = 6 * NFP;
   static constexpr int EPB = (256 / NS) > 64 ? 64 : ((256 / NS) > 0 ? (256 / NS) : 1);  // elements per block
   static constexpr int BLOCK = EPB * NS;
+  // the second tile choice: half of EPB; where EPB is one element whose points do not fill
+  // whole waves (p = 5: 216 points in 4 waves, p = 6: 343 in 6), two elements per block, which
+  // fill 7 and 11 waves
+  static constexpr int EPB2 = EPB > 1 ? EPB / 2 : (NS % 64 != 0 && 2 * NS <= 1024 ? 2 : 1);
 };
 
 // Occupancy targets (waves per SIMD) per kernel and degree; 0 lets the compiler decide.

@@ -227,6 +227,15 @@ std::string build_partition(const HostMesh &G, const int32_t *part, int n_part, 
 // Stage plumbing shared by the single-mesh entry points (fr_kernels.hip) and the partition
 // groups (fr_partition.hip).
 int n_stages(int scheme);  // 4, 5 or 10; 0 for an unknown scheme
+
+// Elements per block of the element kernels for tile choice `epb` (0 or 1) at Ns solution
+// points, as the kernels' Cfg<P>::EPB and Cfg<P>::EPB2 give it: 256/Ns (at least one, at most
+// 64), then half of it, or two where one element leaves lanes of its last wave idle.
+inline int tile_elements(int Ns, int epb) {
+  const int e0 = (256 / Ns) > 64 ? 64 : ((256 / Ns) > 0 ? (256 / Ns) : 1);
+  if (epb == 0) return e0;
+  return e0 > 1 ? e0 / 2 : (Ns % 64 != 0 && 2 * Ns <= 1024 ? 2 : 1);
+}
 // The register update of stage s of `scheme` with step dt (st.mode, coefficients) and the state,
 // output and register arrays that stage reads and writes on the handle's buffers.
 void stage_setup(DeviceMesh &dm, int scheme, int s, double dt, StageArgs &st, const double **X, double **out0,

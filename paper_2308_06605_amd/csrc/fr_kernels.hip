@@ -1110,12 +1110,12 @@ static int launch_stage_t(DeviceMesh &dm, const double *X, StageArgs st, double 
 }
 
 // The tile shapes (the autotuner's choice, DeviceMesh::tile_epb / tile_fbs): elements per block
-// of the element kernels, 256/N_s or half of it, and the face kernel's block of 256, 128 or 64
+// of the element kernels, Cfg::EPB or Cfg::EPB2, and the face kernel's block of 256, 128 or 64
 // threads. Every thread's arithmetic is the same whatever the tiles.
 template <int P, typename real, bool VISC, bool SGS, bool LDG>
 static int launch_stage_tiles(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2,
                               double *ms) {
-  constexpr int E0 = Cfg<P>::EPB, E1 = E0 > 1 ? E0 / 2 : 1;
+  constexpr int E0 = Cfg<P>::EPB, E1 = Cfg<P>::EPB2;
   if (dm.tile_epb == 0) {
     if (dm.tile_fbs == 0) return launch_stage_t<P, real, VISC, SGS, LDG, E0, 256>(dm, X, st, o, r1, r2, ms);
     if (dm.tile_fbs == 1) return launch_stage_t<P, real, VISC, SGS, LDG, E0, 128>(dm, X, st, o, r1, r2, ms);

@@ -994,12 +994,12 @@ int launch32_t(DeviceMesh &dm, const double *X, StageArgs st, double *out0, doub
   return 0;
 }
 
-// The tile shapes, as for the FP64 kernels: elements per block 256/N_s or half of it
+// The tile shapes, as for the FP64 kernels: elements per block Cfg::EPB or Cfg::EPB2
 // (DeviceMesh::tile_epb 0 / 1) and a face block of 256, 128 or 64 threads (tile_fbs 0 / 1 / 2).
 template <int P, bool VISC>
 int launch32_tiles(DeviceMesh &dm, const double *X, StageArgs st, double *o, double *r1, double *r2, double *ms,
                    std::string &err) {
-  constexpr int E0 = Cfg<P>::EPB, E1 = E0 > 1 ? E0 / 2 : 1;
+  constexpr int E0 = Cfg<P>::EPB, E1 = Cfg<P>::EPB2;
   if (dm.tile_epb == 0) {
     if (dm.tile_fbs == 0) return launch32_t<P, VISC, E0, 256>(dm, X, st, o, r1, r2, ms, err);
     if (dm.tile_fbs == 1) return launch32_t<P, VISC, E0, 128>(dm, X, st, o, r1, r2, ms, err);
@@ -1071,7 +1071,7 @@ int group32_t(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
 
 template <int P>
 int group32_tiles(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
-  constexpr int E0 = Cfg<P>::EPB, E1 = E0 > 1 ? E0 / 2 : 1;
+  constexpr int E0 = Cfg<P>::EPB, E1 = Cfg<P>::EPB2;
   if (g.epb == 0) {
     if (g.fbs == 0) return group32_t<P, E0, 256>(g, s, setup, err);
     if (g.fbs == 1) return group32_t<P, E0, 128>(g, s, setup, err);
@@ -1134,9 +1134,8 @@ int group32_create(const std::vector<DeviceMesh *> &meshes, const std::vector<do
   // the tiles of the group's meshes (one setting per group)
   g->epb = meshes[0]->tile_epb;
   g->fbs = meshes[0]->tile_fbs;
-  const int NS = meshes[0]->Ns, NFP = meshes[0]->Nfp;
-  const int E0 = (256 / NS) > 64 ? 64 : ((256 / NS) > 0 ? (256 / NS) : 1);
-  const int epb = g->epb == 0 ? E0 : (E0 > 1 ? E0 / 2 : 1);
+  const int NFP = meshes[0]->Nfp;
+  const int epb = tile_elements(meshes[0]->Ns, g->epb);
   const int fbs = g->fbs == 0 ? 256 : (g->fbs == 1 ? 128 : 64);
   std::vector<Slice32> tab(nm);
   std::vector<int64_t> fe(nm + 1, 0), ff(nm + 1, 0);

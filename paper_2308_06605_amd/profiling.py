@@ -82,6 +82,17 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
     return out
 
 
+def tile_elements(p: int, epb: int) -> int:
+    """Elements per block of the element kernels for tile choice epb (0 or 1) at degree p: 256/Ns
+    (at least one, at most 64), then half of it, or two where one element leaves lanes of its
+    last wave idle (p = 5, 6)."""
+    ns = (p + 1) ** 3
+    e0 = min(64, max(1, 256 // ns))
+    if epb == 0:
+        return e0
+    return e0 // 2 if e0 > 1 else (2 if ns % 64 and 2 * ns <= 1024 else 1)
+
+
 def kernel_source_hash(prec: str = "fp64") -> str:
     h = hashlib.sha256()
     for name in KERNEL_SOURCES[prec]:
@@ -218,7 +229,7 @@ def stage_markdown(stats_csv: str, traffic_json: str, n: int, p: int, prec: str,
     kinds = {"prepass": "k_prepass", "face": "k_face", "volume": "k_volume", "volume_pre": "k_volume_pre"}
     if prec == "fp32":
         kinds = {k: ("k_volume32_pre" if k == "volume_pre" else v + "32") for k, v in kinds.items()}
-    epb = "256/Ns" if tiles[0] == 0 else "half of 256/Ns"
+    epb = f"{tile_elements(p, tiles[0])} elements"
     fbs = (256, 128, 64)[tiles[1]]
     src = kernel_source_hash(prec)
     lines = [f"# Stage kernels, {n}^3 p={p} curved TGV (Roe+BR2, LSRK45), {prec.upper()}", "",
