@@ -244,7 +244,8 @@ int fr_rk_coefficients(int scheme, double *a, double *b, int32_t *n_stages);
 /* ==========================================================================================
  * Batches: many meshes (any degrees, precisions, closures) advanced together. One RK step of
  * every mesh is captured once into a HIP graph, each mesh's stage kernels on a branch of its
- * own, so independent meshes run concurrently; fr_batch_step replays it. The result of every
+ * own, so independent meshes run concurrently, and so are 8 steps whose stages chain through
+ * the fused pre-pass across step boundaries; fr_batch_step replays them. The result of every
  * mesh is bitwise that of fr_rk_step on it alone (same kernels, same order within the mesh).
  * ========================================================================================== */
 typedef struct fr_batch_s *fr_batch_t;
@@ -271,7 +272,9 @@ int fr_batch_create(const fr_mesh_t *meshes, int32_t n, const double *dt, int sc
 int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int scheme, void *hip_stream,
                        int32_t flags, fr_batch_t *out);
 
-/* Enqueue n_steps replays of the captured step on the batch's stream (returns without waiting). */
+/* Enqueue n_steps RK steps on the batch's stream: n_steps / 8 replays of the 8-step graph, then
+ * n_steps % 8 of the one-step graph (returns without waiting). Each replay starts from the
+ * meshes' current states, so states may be changed between calls. */
 int fr_batch_step(fr_batch_t b, int n_steps);
 int fr_batch_set_stream(fr_batch_t b, void *hip_stream);
 int fr_batch_destroy(fr_batch_t b);

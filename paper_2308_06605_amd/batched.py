@@ -13,8 +13,9 @@ default tiles.
 
 Three ways to run the same steps are timed on the same meshes and state:
   sequential  fr_rk_step on each mesh in turn (11 to 15 kernel launches per mesh and step),
-  branches    one captured HIP graph per step, every mesh on a graph branch of its own,
-  multi       one captured HIP graph per step in which each degree's meshes are stepped by the
+  branches    captured HIP graphs (of one step and of 8 chained steps), every mesh on a graph
+              branch of its own,
+  multi       the same graphs, in which each degree's meshes are stepped by the
               multi-mesh kernels: per stage one face and one volume launch covering all of them,
               block b of a launch being some mesh's element or face block (fr_batch_create).
 Throughput is the total DOF-updates per second per RK stage; the roofline fraction is the
@@ -71,7 +72,7 @@ def build(fr, spec, walls=True, prec="fp32"):
     return g, U
 
 
-def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune=True, sizes=(8, 40)):
+def run(n_mesh=48, steps=16, warmup=2, seed=0, walls=True, prec="fp32", autotune=True, sizes=(8, 40)):
     import torch
 
     from . import fr
@@ -168,7 +169,7 @@ def run(n_mesh=48, steps=10, warmup=2, seed=0, walls=True, prec="fp32", autotune
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2308_06605_amd.batched")
     ap.add_argument("--n-mesh", type=int, default=48)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=16, help="timed steps (fr_batch_step: 8-step replays first)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--periodic", action="store_true", help="fully periodic boxes instead of channels")

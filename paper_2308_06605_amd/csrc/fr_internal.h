@@ -178,14 +178,14 @@ int launch_stage32(DeviceMesh &dm, const double *X, StageArgs st, double *o, dou
                    std::string &err);
 
 // Batches of FP32-form meshes advanced by multi-mesh kernels (fr_kernels32.hip): a group holds
-// meshes of one degree (viscous, no closure or LDG, one fusion setting, one tile setting); group32_step enqueues
-// one RK step of every mesh with one launch per kernel and stage covering all of them. 0 or a negative
-// FR_ERR_* code with `err` set.
+// meshes of one degree (viscous, no closure or LDG, one fusion setting, one tile setting);
+// group32_step enqueues `steps` RK steps of every mesh with one launch per kernel and stage
+// covering all of them. 0 or a negative FR_ERR_* code with `err` set.
 struct Group32;
 bool group32_eligible(const DeviceMesh &dm);
 int group32_create(const std::vector<DeviceMesh *> &meshes, const std::vector<double> &dt, int scheme, Group32 **out,
                    std::string &err);
-int group32_step(Group32 *g, void *stream, std::string &err);
+int group32_step(Group32 *g, void *stream, int steps, std::string &err);
 void group32_destroy(Group32 *g);
 int group32_items(const Group32 *g, int64_t *elem_items, int64_t *face_items);
 

@@ -1790,13 +1790,17 @@ int fr_get_eddy_viscosity(fr_mesh_t m, double *nu) {
 // ------------------------------------------------------------------------------------------
 }  // extern "C"
 
+// Steps per replay of a batch's chained graph: inside it every stage but the first runs its
+// pre-pass in the previous stage's volume kernel, across step boundaries too.
+static constexpr int kBatchChain = 8;
+
 struct fr_batch_s {
   uint64_t magic;
   std::vector<fr_mesh_t> meshes;
   std::vector<Group32 *> groups;  // meshes stepped by the multi-mesh kernels, one group per degree
   hipStream_t stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};  // one step; kBatchChain steps
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   int device = 0;
 };
 
@@ -1878,8 +1882,8 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
   std::vector<hipStream_t> br(nbr, nullptr);
   std::vector<hipEvent_t> join(nbr, nullptr);
   hipEvent_t fork = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   int rc = FR_OK;
   std::string msg;
   auto chk = [&](hipError_t e, const char *what) {
@@ -1889,21 +1893,23 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
     }
     return e == hipSuccess;
   };
-  bool capturing = false;
   if (chk(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate") &&
       chk(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate")) {
     for (int i = 0; i < nbr && rc == FR_OK; ++i)
       if (chk(hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking), "hipStreamCreate"))
         chk(hipEventCreateWithFlags(&join[i], hipEventDisableTiming), "hipEventCreate");
   }
-  if (rc == FR_OK && chk(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) {
-    capturing = true;
+  // two graphs: one step, and kBatchChain steps whose stages chain through the fused pre-pass
+  // (each replay starts with a stand-alone pre-pass, so state changes between replays are safe)
+  for (int gi = 0; gi < 2 && rc == FR_OK; ++gi) {
+    const int steps = gi == 0 ? 1 : kBatchChain;
+    if (!chk(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) break;
     chk(hipEventRecord(fork, cs), "hipEventRecord");
     for (int b = 0; b < nbr && rc == FR_OK; ++b) {
       if (!chk(hipStreamWaitEvent(br[b], fork, 0), "hipStreamWaitEvent")) break;
       if (b < (int)groups.size()) {
         std::string gerr;
-        const int r = group32_step(groups[b], br[b], gerr);
+        const int r = group32_step(groups[b], br[b], steps, gerr);
         if (r) {
           rc = r;
           msg = gerr;
@@ -1914,7 +1920,7 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
         DeviceMesh &dm = meshes[i]->dm;
         void *saved = dm.stream;
         dm.stream = br[b];
-        int r = run_steps(meshes[i], dt[i], scheme, 1, nullptr);
+        int r = run_steps(meshes[i], dt[i], scheme, steps, nullptr);
         dm.stream = saved;
         if (r) {
           rc = r;
@@ -1925,12 +1931,10 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
       if (!chk(hipEventRecord(join[b], br[b]), "hipEventRecord")) break;
       chk(hipStreamWaitEvent(cs, join[b], 0), "hipStreamWaitEvent");
     }
-    hipError_t e = hipStreamEndCapture(cs, &graph);
-    capturing = false;
+    hipError_t e = hipStreamEndCapture(cs, &graph[gi]);
     chk(e, "hipStreamEndCapture");
+    if (rc == FR_OK) chk(hipGraphInstantiate(&exec[gi], graph[gi], nullptr, nullptr, 0), "hipGraphInstantiate");
   }
-  (void)capturing;
-  if (rc == FR_OK) chk(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
   for (int i = 0; i < nbr; ++i) {
     if (join[i]) (void)hipEventDestroy(join[i]);
     if (br[i]) (void)hipStreamDestroy(br[i]);
@@ -1938,8 +1942,10 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
   if (fork) (void)hipEventDestroy(fork);
   if (cs) (void)hipStreamDestroy(cs);
   if (rc != FR_OK) {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int gi = 0; gi < 2; ++gi) {
+      if (exec[gi]) (void)hipGraphExecDestroy(exec[gi]);
+      if (graph[gi]) (void)hipGraphDestroy(graph[gi]);
+    }
     for (Group32 *g : groups) group32_destroy(g);
     return fail(rc, "batch capture failed: " + msg);
   }
@@ -1948,8 +1954,10 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
   b->meshes.assign(meshes, meshes + n);
   b->groups = groups;
   b->stream = (hipStream_t)hip_stream;
-  b->graph = graph;
-  b->exec = exec;
+  for (int gi = 0; gi < 2; ++gi) {
+    b->graph[gi] = graph[gi];
+    b->exec[gi] = exec[gi];
+  }
   b->device = dev;
   *out = b;
   return FR_OK;
@@ -1958,7 +1966,8 @@ int fr_batch_create_ex(const fr_mesh_t *meshes, int32_t n, const double *dt, int
 int fr_batch_step(fr_batch_t b, int n_steps) {
   if (!valid_batch(b)) return fail(FR_ERR_ARG, "not a batch handle");
   if (n_steps < 0) return fail(FR_ERR_ARG, "n_steps must be >= 0");
-  for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->exec, b->stream));
+  for (int k = 0; k < n_steps / kBatchChain; ++k) HIPCHK(hipGraphLaunch(b->exec[1], b->stream));
+  for (int k = 0; k < n_steps % kBatchChain; ++k) HIPCHK(hipGraphLaunch(b->exec[0], b->stream));
   return FR_OK;
 }
 
@@ -1972,8 +1981,10 @@ int fr_batch_destroy(fr_batch_t b) {
   if (!b) return FR_OK;
   if (!valid_batch(b)) return fail(FR_ERR_ARG, "not a batch handle");
   (void)hipStreamSynchronize(b->stream);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (int gi = 0; gi < 2; ++gi) {
+    if (b->exec[gi]) (void)hipGraphExecDestroy(b->exec[gi]);
+    if (b->graph[gi]) (void)hipGraphDestroy(b->graph[gi]);
+  }
   for (Group32 *g : b->groups) group32_destroy(g);
   b->magic = 0;
   delete b;

@@ -1037,10 +1037,11 @@ struct Group32Impl {
   int64_t items_e = 0, items_f = 0;
 };
 
-// setup: check that the item counts fit a launch; otherwise enqueue one RK step of every mesh of
-// the group
+// setup: check that the item counts fit a launch; otherwise enqueue `steps` RK steps of every mesh
+// of the group. With fusion every stage but the first finds its pre-pass done by the previous
+// stage's volume kernel, across step boundaries too, as fr_rk_step's run of steps does.
 template <int P, int EPB, int FBS>
-int group32_t(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
+int group32_t(Group32Impl &g, hipStream_t s, bool setup, int steps, std::string &err) {
   constexpr int TB = EPB * Cfg<P>::NS;
   if (setup) {
     if (g.items_e * TB > (int64_t)UINT32_MAX || g.items_f * FBS > (int64_t)UINT32_MAX) {
@@ -1050,47 +1051,50 @@ int group32_t(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
     return 0;
   }
   const dim3 ge((unsigned)g.items_e), gf((unsigned)g.items_f);
-  for (int st = 0; st < g.ns; ++st) {
-    if (st == 0 || !g.fuse) {
-      hipLaunchKernelGGL((k_prepass32_multi<P, true, EPB>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st, g.ops,
-                         g.opsd);
+  for (int step = 0; step < steps; ++step) {
+    for (int st = 0; st < g.ns; ++st) {
+      const bool first = step == 0 && st == 0, last = step == steps - 1 && st == g.ns - 1;
+      if (first || !g.fuse) {
+        hipLaunchKernelGGL((k_prepass32_multi<P, true, EPB>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st,
+                           g.ops, g.opsd);
+        HIPCHK32(hipGetLastError());
+      }
+      hipLaunchKernelGGL((k_face32_multi<P, true, FBS>), gf, dim3(FBS), 0, s, g.tab, g.first_f, g.nm);
+      HIPCHK32(hipGetLastError());
+      if (g.fuse && !last)
+        hipLaunchKernelGGL((k_volume32_multi<P, true, EPB, true>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st,
+                           g.ops, g.opsd);
+      else
+        hipLaunchKernelGGL((k_volume32_multi<P, true, EPB, false>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st,
+                           g.ops, g.opsd);
       HIPCHK32(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_face32_multi<P, true, FBS>), gf, dim3(FBS), 0, s, g.tab, g.first_f, g.nm);
-    HIPCHK32(hipGetLastError());
-    if (g.fuse && st < g.ns - 1)
-      hipLaunchKernelGGL((k_volume32_multi<P, true, EPB, true>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st,
-                         g.ops, g.opsd);
-    else
-      hipLaunchKernelGGL((k_volume32_multi<P, true, EPB, false>), ge, dim3(TB), 0, s, g.tab, g.first_e, g.nm, st,
-                         g.ops, g.opsd);
-    HIPCHK32(hipGetLastError());
   }
   return 0;
 }
 
 template <int P>
-int group32_tiles(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
+int group32_tiles(Group32Impl &g, hipStream_t s, bool setup, int steps, std::string &err) {
   constexpr int E0 = Cfg<P>::EPB, E1 = Cfg<P>::EPB2;
   if (g.epb == 0) {
-    if (g.fbs == 0) return group32_t<P, E0, 256>(g, s, setup, err);
-    if (g.fbs == 1) return group32_t<P, E0, 128>(g, s, setup, err);
-    return group32_t<P, E0, 64>(g, s, setup, err);
+    if (g.fbs == 0) return group32_t<P, E0, 256>(g, s, setup, steps, err);
+    if (g.fbs == 1) return group32_t<P, E0, 128>(g, s, setup, steps, err);
+    return group32_t<P, E0, 64>(g, s, setup, steps, err);
   }
-  if (g.fbs == 0) return group32_t<P, E1, 256>(g, s, setup, err);
-  if (g.fbs == 1) return group32_t<P, E1, 128>(g, s, setup, err);
-  return group32_t<P, E1, 64>(g, s, setup, err);
+  if (g.fbs == 0) return group32_t<P, E1, 256>(g, s, setup, steps, err);
+  if (g.fbs == 1) return group32_t<P, E1, 128>(g, s, setup, steps, err);
+  return group32_t<P, E1, 64>(g, s, setup, steps, err);
 }
 
-int group32_dispatch(Group32Impl &g, hipStream_t s, bool setup, std::string &err) {
+int group32_dispatch(Group32Impl &g, hipStream_t s, bool setup, int steps, std::string &err) {
   switch (g.p) {
-    case 1: return group32_tiles<1>(g, s, setup, err);
-    case 2: return group32_tiles<2>(g, s, setup, err);
-    case 3: return group32_tiles<3>(g, s, setup, err);
-    case 4: return group32_tiles<4>(g, s, setup, err);
-    case 5: return group32_tiles<5>(g, s, setup, err);
-    case 6: return group32_tiles<6>(g, s, setup, err);
-    case 7: return group32_tiles<7>(g, s, setup, err);
+    case 1: return group32_tiles<1>(g, s, setup, steps, err);
+    case 2: return group32_tiles<2>(g, s, setup, steps, err);
+    case 3: return group32_tiles<3>(g, s, setup, steps, err);
+    case 4: return group32_tiles<4>(g, s, setup, steps, err);
+    case 5: return group32_tiles<5>(g, s, setup, steps, err);
+    case 6: return group32_tiles<6>(g, s, setup, steps, err);
+    case 7: return group32_tiles<7>(g, s, setup, steps, err);
     default: err = "multi-mesh groups take p = 1..7"; return -5;
   }
 }
@@ -1192,7 +1196,7 @@ int group32_create(const std::vector<DeviceMesh *> &meshes, const std::vector<do
     err = "device tables of a mesh group";
     return -4;
   }
-  int rc = group32_dispatch(*g, nullptr, true, err);
+  int rc = group32_dispatch(*g, nullptr, true, 0, err);
   if (rc) {
     free_group32(g);
     return rc;
@@ -1201,8 +1205,8 @@ int group32_create(const std::vector<DeviceMesh *> &meshes, const std::vector<do
   return 0;
 }
 
-int group32_step(Group32 *g, void *stream, std::string &err) {
-  return group32_dispatch(*reinterpret_cast<Group32Impl *>(g), (hipStream_t)stream, false, err);
+int group32_step(Group32 *g, void *stream, int steps, std::string &err) {
+  return group32_dispatch(*reinterpret_cast<Group32Impl *>(g), (hipStream_t)stream, false, steps, err);
 }
 
 void group32_destroy(Group32 *g) {

@@ -655,6 +655,7 @@ class Batch:
         self.h = h
 
     def step(self, n_steps: int = 1):
+        """n_steps RK steps: replays of the captured 8-step graph, then of the one-step graph."""
         _check(load().fr_batch_step(self.h, int(n_steps)))
 
     def close(self):

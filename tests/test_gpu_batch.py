@@ -93,11 +93,12 @@ def test_batch_matches_single_meshes(scheme, multi):
         single_meshes.append(g2)
         nets.append(net2)
     b = fr.Batch(batch_meshes, dts, scheme, multi=multi)
-    for rep in range(3):
-        b.step(2)
+    # 2 steps: the one-step graph twice; 9: the chained 8-step graph, then the one-step graph
+    for rep, nsteps in enumerate((2, 9, 2)):
+        b.step(nsteps)
         torch.cuda.synchronize()
         for g2, dt in zip(single_meshes, dts):
-            g2.rk_step(dt, scheme, 2)
+            g2.rk_step(dt, scheme, nsteps)
         torch.cuda.synchronize()
         for i, (g, g2) in enumerate(zip(batch_meshes, single_meshes)):
             Ub, Us = g.get_state(), g2.get_state()
@@ -113,6 +114,43 @@ def test_batch_matches_single_meshes(scheme, multi):
     for net in nets:
         if net is not None:
             net.close()
+
+
+def test_many_meshes_in_one_group():
+    """33 FP32-form meshes of one degree and one tile setting, of 27 to 80 elements in uneven
+    order: one multi-mesh group whose launches cover all of them, so a block's mesh is found by
+    bisection over 33 prefix sums. Every mesh ends bit for bit where fr_rk_step takes it."""
+    import torch
+
+    fr = _fr()
+    rng = np.random.default_rng(5)
+    shapes = [tuple(int(x) for x in rng.integers(3, 6, 3)) for _ in range(33)]
+    meshes, singles, dts = [], [], []
+    for i, sh in enumerate(shapes):
+        m = I.box_mesh(sh, q=2, curve_amp=0.03)
+        p0 = P0 * (1 + 0.01 * i)
+        gs = []
+        for _ in range(2):
+            g = fr.FRMesh(m, 2, mu=MU, flux="roe", prec="fp32", ref_rho=1.0, ref_p=p0)
+            X = g.sol_coords()
+            g.set_state(I.state_from_coords(X, I.tgv_state) + I.random_smooth_perturbation(X, seed=i, amp=0.02))
+            gs.append(g)
+        meshes.append(gs[0])
+        singles.append(gs[1])
+        dts.append(5e-4 * (1 + 0.02 * i))
+    b = fr.Batch(meshes, dts, "lsrk45")
+    for rep, nsteps in enumerate((2, 8)):
+        b.step(nsteps)
+        torch.cuda.synchronize()
+        for g, dt in zip(singles, dts):
+            g.rk_step(dt, "lsrk45", nsteps)
+        for i, (g, g2) in enumerate(zip(meshes, singles)):
+            Ub, Us = g.get_state(), g2.get_state()
+            assert np.isfinite(Ub).all()
+            assert np.array_equal(Ub, Us), (rep, i, shapes[i])
+    b.close()
+    for g in meshes + singles:
+        g.close()
 
 
 def test_batch_errors():
