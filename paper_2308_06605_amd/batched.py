@@ -134,13 +134,8 @@ def run(n_mesh=48, steps=16, warmup=2, seed=0, walls=True, prec="fp32", autotune
     finite = all(np.isfinite(u).all() for u in U_seq)
     for g in meshes:
         g.close()
-    # the two-pass minimum bytes per stage of every mesh (SURVEY's per-element rule)
-    stage_bytes = 0
-    for s in specs:
-        n_, p_ = s["n"], s["p"]
-        Ns, Nf = (p_ + 1) ** 3, 6 * (p_ + 1) ** 2
-        per = 8 * (45 * Ns + 44 * Nf) if prec == "fp64" else 8 * 25 * Ns + 4 * (20 * Ns + 44 * Nf)
-        stage_bytes += per * n_ ** 3
+    # the two-pass minimum bytes per stage of every mesh
+    stage_bytes = sum(algorithmic_bytes(s["p"], prec)["stage_min"] * s["n"] ** 3 for s in specs)
     for rec in [timed["branches"], timed["multi"]]:
         rec["roofline_frac"] = stage_bytes / (rec["ms_per_step"] / stages * 1e-3) / 8e12
     geo = "channel meshes (isothermal walls in y)" if walls else "periodic box meshes"
