@@ -34,6 +34,7 @@ import time
 import numpy as np
 
 from . import inputs as I
+from .profiling import algorithmic_bytes
 
 GAMMA = 1.4
 MU = 1e-4
