@@ -47,6 +47,9 @@ CASES = [  # (n, p, prec, viscous, closure, force)
     (3, 7, "fp32", "br2", None, None),
     (4, 3, "fp32", "br2", "tiles", None),
     (3, 2, "fp32", "br2", "tiles", None),
+    # at p = 5 and 6 the second tile choice is two elements per block
+    (3, 5, "fp32", "br2", "tiles", None),
+    (3, 6, "fp32", "br2", "tiles", None),
 ]
 
 
