@@ -119,6 +119,27 @@ def cpu_baseline(mesh, p, U, mu, flux, extra=()):
     return out
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 3) -> float:
+    """GB/s of a plain device-to-device copy of nbytes (read + write counted), median of reps,
+    HIP events on the current stream: the practical HBM ceiling the roofline is also given
+    against."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    return 2 * nbytes / (float(np.median(ts)) * 1e-3) / 1e9
+
+
 def run_config(fr, inputs, n, p, prec, args, mu, curved=True):
     """Build the curved TGV workload on n^3 elements at degree p in the given precision, pick
     tiles (autotuner or --tiles), run the warm-up and time args.steps RK steps with HIP events on
@@ -154,12 +175,29 @@ def run_config(fr, inputs, n, p, prec, args, mu, curved=True):
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ms_step = e0.elapsed_time(e1) / args.steps
+    # the same K steps repeated (not part of `value`), and the residual alone
+    repeats = []
+    for _ in range(args.repeats):
+        e0.record(stream)
+        g.rk_step(args.dt, args.scheme, args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        repeats.append(e0.elapsed_time(e1) / args.steps)
+    Rt = torch.empty((mesh.n_elem, 5, (p + 1) ** 3), dtype=torch.float64, device="cuda")
+    res_ms = []
+    for _ in range(1 + args.repeats):
+        e0.record(stream)
+        g.residual(out=Rt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res_ms.append(e0.elapsed_time(e1))
+    del Rt
     dof = mesh.n_elem * (p + 1) ** 3
     stage_ms = ms_step / stages
     # per-kernel mean launch durations (HIP events on the launch stream); with fusion the
     # pre-pass runs once per run of stages and every other stage is face + volume_pre
     kms = {k: v for k, v in g.profile_stages(args.dt, args.scheme, 2).items() if v > 0}
-    ab = algorithmic_bytes(p, prec)
+    ab = algorithmic_bytes(p, prec, affine=not curved)
     E = mesh.n_elem
     gbs = {k: ab[k] * E / (kms[k] * 1e-3) / 1e9 for k in kms}
     per_stage = ("face", "volume_pre") if "volume_pre" in kms else ("prepass", "face", "volume")
@@ -187,6 +225,9 @@ def run_config(fr, inputs, n, p, prec, args, mu, curved=True):
                      f"{'FP64' if prec == 'fp64' else 'FP32 operators/fluxes, FP64 state and mass'}"),
         "n": n, "n_elem": E, "dof": dof, "p": p, "prec": prec,
         "value": dof * stages / (ms_step * 1e-3), "ms_per_step": ms_step, "stage_ms": stage_ms,
+        "repeats_ms_per_step": repeats,
+        "median_value": dof * stages / (float(np.median([ms_step, *repeats])) * 1e-3),
+        "residual_ms": float(np.median(res_ms[1:])) if len(res_ms) > 1 else res_ms[0],
         "tiles": {"elements_per_block": tile_elements(p, tiles[0]), "epb_choice": int(tiles[0]),
                   "face_block": (256, 128, 64)[tiles[1]], "fused_prepass": fused,
                   "autotune_ms_per_stage": None if tile_ms is None else [float(x) for x in tile_ms]},
@@ -194,8 +235,10 @@ def run_config(fr, inputs, n, p, prec, args, mu, curved=True):
                      "frac": stage_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": " + ".join(kernel_name(k, prec) for k in per_stage) + " (one RK stage)",
                      "bytes_per_stage": stage_bytes,
-                     "bytes_rule": ("8 (45 Ns + 44 Nf) per element" if prec == "fp64"
-                                    else "8 * 25 Ns + 4 (20 Ns + 44 Nf) per element"),
+                     "bytes_rule": {("fp64", True): "8 (45 Ns + 44 Nf) per element",
+                                    ("fp32", True): "8 * 25 Ns + 4 (20 Ns + 44 Nf) per element",
+                                    ("fp64", False): "8 (25 Ns + 40 Nf) per element (affine elements)",
+                                    ("fp32", False): "8 * 25 Ns + 4 * 40 Nf per element (affine elements)"}[(prec, curved)],
                      "dominant_kernel": {"kernel": kernel_name(dominant, prec),
                                          "bytes_per_launch": ab[dominant] * E,
                                          "mean_launch_ms": kms[dominant],
@@ -226,6 +269,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other precision and degree (FP32 form at this size, 32^3 p=7 in both)")
+    ap.add_argument("--repeats", type=int, default=4,
+                    help="repeat the K timed steps this many more times (median_value; not `value`)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer once (a known-size "
                          "dispatch that scales the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -245,25 +290,33 @@ def main():
     curved = not args.affine
     main_run = run_config(fr, inputs, args.n, args.p, args.prec, args, mu, curved)
     mesh, U = main_run.pop("_mesh"), main_run.pop("_U")
+    cgbs = copy_bandwidth()
+    main_run["roofline"]["copy_gbs"] = cgbs
+    main_run["roofline"]["frac_of_copy"] = main_run["roofline"]["achieved"] / cgbs
 
     variants = {}
     p7 = None
     if not args.no_variants:
         other = "fp32" if args.prec == "fp64" else "fp64"
         plan = [(other, args.n, args.p)]
+        plan = [(prec, n, p, curved) for prec, n, p in plan]
         if args.p == 3 and args.n == 64:
-            # the precision variant's p = 7 workload, 32^3 (the same 16.8M DOF), in both forms
-            plan += [("fp64", 32, 7), ("fp32", 32, 7)]
-        for prec, n, p in plan:
-            r = run_config(fr, inputs, n, p, prec, args, mu, curved)
+            # the precision variant's p = 7 workload, 32^3 (the same 16.8M DOF), in both forms,
+            # and the uniform (affine) 64^3 box in FP64
+            plan += [("fp64", 32, 7, curved), ("fp32", 32, 7, curved)]
+            if curved:
+                plan += [("fp64", 64, 3, False)]
+        for prec, n, p, cv in plan:
+            r = run_config(fr, inputs, n, p, prec, args, mu, cv)
             m7, U7 = r.pop("_mesh"), r.pop("_U")
             if p == 7 and p7 is None:
                 p7 = (m7, U7)
             r["speedup_vs_fp64_same_size"] = None
-            variants[f"{prec}_n{n}_p{p}"] = r
+            variants[f"{prec}_n{n}_p{p}" + ("" if cv == curved else "_affine")] = r
         runs = [main_run, *variants.values()]
         for r in variants.values():
-            ref = [q for q in runs if (q["n"], q["p"], q["prec"]) == (r["n"], r["p"], "fp64")]
+            ref = [q for q in runs if (q["n"], q["p"], q["prec"], q["workload"].split(",")[1])
+                   == (r["n"], r["p"], "fp64", r["workload"].split(",")[1])]
             if r["prec"] == "fp32" and ref:
                 ref = ref[0]
                 r["speedup_vs_fp64_same_size"] = ref["ms_per_step"] / r["ms_per_step"]

@@ -41,7 +41,7 @@ KERNEL_SOURCES = {"fp64": ("fr_kernels.hip", "fr_device.h", "fr_internal.h"),
                   "fp32": ("fr_kernels32.hip", "fr_device.h", "fr_internal.h")}
 
 
-def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
+def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True, affine: bool = False):
     """HBM bytes per element per stage that each kernel must move (every input read once,
     every output written once); the state and RK registers are always FP64.
 
@@ -59,6 +59,10 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
     p = 3. `stage_min` is the two-pass minimum of a stage that reads its inputs in both passes:
     FP64 8 (45 Ns + 44 Nf); FP32 form (FP64 state, FP32 geometry and face data)
     8 * 25 Ns + 4 (20 Ns + 44 Nf). The roofline of the whole stage is taken on it.
+    affine: the two-pass minimum of a mesh of affine elements, whose metric terms and face
+    normals are constant per element and face: FP64 8 (25 Ns + 40 Nf) (680 B/DOF at p = 3), FP32
+    form 8 * 25 Ns + 4 * 40 Nf. The kernels' own bytes do not change: they read the terms per
+    point on every mesh.
     """
     n = p + 1
     Ns, Nfp = n ** 3, n * n
@@ -76,6 +80,8 @@ def algorithmic_bytes(p: int, prec: str = "fp64", viscous: bool = True):
         k2 = 3 * Nfp * (2 * (4 * nv + 8 * 3) + 8 * 4 + 4 * 9 + 8)
         k3 = 8 * 20 * Ns + 8 * 10 * Ns + (4 * 9 + 8) * Nf
         stage_min = 8 * 25 * Ns + 4 * (20 * Ns + 44 * Nf)
+    if affine:
+        stage_min = 8 * (25 * Ns + 40 * Nf) if prec == "fp64" else 8 * 25 * Ns + 4 * 40 * Nf
     out = {"prepass": k1, "face": k2, "volume": k3, "stage_min": stage_min}
     # the volume kernel with the next stage's pre-pass adds the pre-pass's writes
     out["volume_pre"] = k3 + (8 * nv * Nf if prec == "fp64" else (4 * nv + 8 * 3) * Nf)

@@ -64,3 +64,14 @@ def test_kernel_names():
                                                   "volume_pre": "k_volume_pre"}[key]
     assert bench.kernel_name("volume_pre", "fp32") == "k_volume32_pre"
     assert bench.kernel_name("prepass", "fp32") == "k_prepass32"
+
+
+def test_affine_two_pass_minimum():
+    """On affine elements the metric terms and face normals are constant per element and face,
+    so the two-pass minimum drops them: 8 (25 N_s + 40 N_f), 680 B/DOF at p = 3 and 440 at
+    p = 7; the kernels' own bytes are unchanged (they read the per-point terms on every mesh)."""
+    a3, c3 = bench.algorithmic_bytes(3, "fp64", affine=True), bench.algorithmic_bytes(3, "fp64")
+    assert a3["stage_min"] / 64 == 680.0
+    assert bench.algorithmic_bytes(7, "fp64", affine=True)["stage_min"] / 512 == 440.0
+    assert {k: v for k, v in a3.items() if k != "stage_min"} == {k: v for k, v in c3.items() if k != "stage_min"}
+    assert bench.algorithmic_bytes(3, "fp32", affine=True)["stage_min"] / 64 == 440.0
