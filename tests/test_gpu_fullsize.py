@@ -34,11 +34,12 @@ def _fr():
 P0 = 1.0 / (1.4 * 0.01)
 
 
-@pytest.mark.parametrize("n,p", [(64, 3), (32, 7)])
-def test_sampled_parity_full_size(n, p):
+@pytest.mark.parametrize("n,p,curved", [(64, 3, True), (32, 7, True), (64, 3, False)])
+def test_sampled_parity_full_size(n, p, curved):
+    """The curved benchmark meshes and the uniform 64^3 box, 96 sampled elements."""
     fr = _fr()
     mu = 1.0 / 1600.0
-    m = I.box_mesh(n, q=p, curve_amp=0.05)
+    m = I.box_mesh(n, q=p, curve_amp=0.05 if curved else 0.0)
     g = fr.FRMesh(m, p, mu=mu, flux="roe")
     X = g.sol_coords()
     U = I.state_from_coords(X, I.tgv_state)
@@ -53,7 +54,7 @@ def test_sampled_parity_full_size(n, p):
     scale = np.abs(Rl).max(axis=(0, 2))
     e = np.abs(R[sample] - Rl).max(axis=(0, 2)) / scale
     f = np.abs(Ro - Rl).max(axis=(0, 2)) / scale
-    print(f"{n}^3 p={p}: gpu err {e} oracle floor {f}", flush=True)
+    print(f"{n}^3 p={p} {'curved' if curved else 'uniform'}: gpu err {e} oracle floor {f}", flush=True)
     assert np.all(e <= np.maximum(1e-12, 2 * f)), (e, f)
     assert np.isfinite(R).all()
 
