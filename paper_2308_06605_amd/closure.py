@@ -433,6 +433,32 @@ def evaluate(model_path, ref_path, out=None):
     return res
 
 
+def scale_check(t_end: float, every: float, out: str, dt_fine=None, dt_coarse=None):
+    """Implicit LES at the coarse resolution against the fine run: the TGV at both (no closure),
+    the fine run's energy filtered to the coarse space and its dissipation rate, the coarse run's
+    energy and dissipation rate at the same times. Where the coarse run dissipates more than the
+    fine one, a positive eddy viscosity adds to an excess."""
+    global DT_FINE, DT_COARSE
+    if dt_fine:
+        DT_FINE = dt_fine
+    if dt_coarse:
+        DT_COARSE = dt_coarse
+    ref_path = out + ".ref.npz"
+    gen("tgv", t_end, every, ref_path, reference=True)
+    ref = np.load(ref_path)
+    t = ref["t"]
+    ek, dek, _, _ = coarse_run(None, t)
+    res = {"fine": list(FINE), "coarse": list(COARSE), "dt_fine": DT_FINE, "dt_coarse": DT_COARSE,
+           "t": t.tolist(), "ek_filtered": ref["ek_filtered"].tolist(), "eps_fine": (-ref["dek_fine"]).tolist(),
+           "ek_coarse": ek.tolist(), "eps_coarse": (-dek).tolist()}
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    for i in range(len(t)):
+        log(f"t={t[i]:.2f} E_k filtered fine {res['ek_filtered'][i]:.6f} coarse {ek[i]:.6f} | "
+            f"eps fine {res['eps_fine'][i]:.5f} coarse {-dek[i]:.5f}")
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2308_06605_amd.closure")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -452,7 +478,13 @@ def main(argv=None):
     c.add_argument("--model", required=True)
     c.add_argument("--ref", required=True)
     c.add_argument("--out", default=None)
-    for q in (a, b, c):
+    s = sub.add_parser("scale", help="implicit LES at the coarse resolution against the fine run")
+    s.add_argument("--t-end", type=float, default=7.0)
+    s.add_argument("--every", type=float, default=0.5)
+    s.add_argument("--dt-fine", type=float, default=None)
+    s.add_argument("--dt-coarse", type=float, default=None)
+    s.add_argument("--out", required=True)
+    for q in (a, b, c, s):
         q.add_argument("--fine", type=int, nargs=2, default=None, metavar=("N", "P"))
         q.add_argument("--coarse", type=int, nargs=2, default=None, metavar=("N", "P"))
     a.add_argument("--reference", action="store_true", help="filtered energies only (no targets)")
@@ -460,6 +492,8 @@ def main(argv=None):
     configure(args.fine, args.coarse)
     if args.cmd == "gen":
         gen(args.ic, args.t_end, args.every, args.out, args.keep_state_at, args.reference)
+    elif args.cmd == "scale":
+        scale_check(args.t_end, args.every, args.out, args.dt_fine, args.dt_coarse)
     elif args.cmd == "train":
         train_model(args.data, args.val, args.out, epochs=args.epochs, lr=args.lr)
     else:
