@@ -70,3 +70,17 @@ def test_bad_part_maps_are_rejected():
     part[0] = -1
     with pytest.raises(fr.FRError):
         fr.partition_host(m, 2, part, 0)
+
+
+def test_block_map_of_the_partition_benchmark():
+    """partbench's block map: a 2x2x2 cut of a 6^3 box gives eight parts of 27 elements, each a
+    3x3x3 box of elements, part index bx-fastest."""
+    from paper_2308_06605_amd import partbench as PB
+
+    n = 6
+    part = PB.block_map(n, (2, 2, 2))
+    assert np.array_equal(np.bincount(part), np.full(8, 27))
+    e = np.arange(n ** 3)
+    ie, je, ke = e % n, (e // n) % n, e // (n * n)
+    assert np.array_equal(part, (ie // 3) + 2 * ((je // 3) + 2 * (ke // 3)))
+    assert np.array_equal(np.unique(PB.block_map(n, (3, 1, 2))), np.arange(6))
