@@ -673,6 +673,41 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
       }
     }
     __syncthreads();
+    if constexpr (NF <= NS) {
+      // at most one face point per thread (p = 5, 6): its line and interpolation weights once,
+      // then every group; the same sums as the items below
+      if (act && t < NF) {
+        int f, kk, b0, stride;
+        line(t, f, kk, b0, stride);
+        const bool hi = f & 1;
+        float cf[N];
+        double cd[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          cf[c] = hi ? ops.lp[c] : ops.lm[c];
+          cd[c] = hi ? opsd.lp[c] : opsd.lm[c];
+        }
+#pragma unroll
+        for (int grp = 0; grp < NGRP - 1; ++grp) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            const float *src = grp == 0 ? &sU[v * NS] : &sJ[(v * 3 + grp - 1) * NS];
+            float acc = 0;
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc += cf[c] * src[b0 + c * stride];
+            face_store<NFP>(acc, &face32[((e * 6 + f) * 20 + 5 * grp + v) * NFP + kk]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          double acc = 0;
+#pragma unroll
+          for (int c = 0; c < N; ++c) acc += cd[c] * sM[i * NS + b0 + c * stride];
+          face_store<NFP>(acc, &facem[((e * 6 + f) * 3 + i) * NFP + kk]);
+        }
+      }
+      return;
+    }
     if (act) {
       for (int q = t; q < NGRP * NF; q += NS) {
         const int grp = q / NF;

@@ -47,6 +47,7 @@ CASES = [
     (4, "ssprk104", 0.0, "br2", "fp32"),
     (4, "lsrk45", 1e-3, "br2", "fp32"),
     (5, "rk4", 1e-3, "br2", "fp32"),
+    (6, "lsrk45", 1e-3, "br2", "fp32"),
     (2, "lsrk45", 1e-3, "br2", "fp32 walls"),
     # 75 elements: a ragged last block at every tile choice of p = 3 (4 or 2 elements per block)
     (3, "lsrk45", 1e-3, "br2", "ragged"),
