@@ -673,12 +673,12 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
       }
     }
     __syncthreads();
-    if constexpr (NF <= NS) {
-      // at most one face point per thread (p = 5, 6): its line and interpolation weights once,
-      // then every group; the same sums as the items below
-      if (act && t < NF) {
+    if constexpr (FR_TAIL_PER_POINT32(P)) {
+      // whole face points per thread: each point's line and interpolation weights once, then
+      // every group; the same sums as the items below
+      for (int fp = t; act && fp < NF; fp += NS) {
         int f, kk, b0, stride;
-        line(t, f, kk, b0, stride);
+        line(fp, f, kk, b0, stride);
         const bool hi = f & 1;
         float cf[N];
         double cd[N];

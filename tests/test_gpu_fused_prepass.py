@@ -33,6 +33,9 @@ CASES = [
     # p, scheme, mu, viscous, extra
     (3, "lsrk45", 1e-3, "br2", None),
     (3, "rk4", 1e-3, "br2", None),
+    (0, "lsrk45", 1e-3, "br2", None),
+    (1, "rk4", 1e-3, "br2", None),
+    (1, "lsrk45", 1e-3, "br2", "fp32"),
     (2, "ssprk104", 1e-3, "br2", None),
     (4, "rk4", 1e-3, "br2", None),
     (5, "lsrk45", 1e-3, "br2", None),
@@ -63,10 +66,10 @@ def test_steps_in_one_call_equal_separate_calls(p, scheme, mu, viscous, extra):
         m = I.box_mesh((4, 5, 4), q=2, periodic=(True, False, True), curve_amp=0.02, curve_mode="mixed")
         kw = dict(bc_tag=I.boundary_tags(m), wall_T=p0)
     elif extra is not None and "ragged" in extra:
-        m = I.box_mesh((5, 5, 3), q=min(p, 3), curve_amp=0.04)
+        m = I.box_mesh((5, 5, 3), q=max(1, min(p, 3)), curve_amp=0.04)
         kw = {}
     else:
-        m = I.box_mesh(4, q=min(p, 3), curve_amp=0.04)
+        m = I.box_mesh(4, q=max(1, min(p, 3)), curve_amp=0.04)
         kw = {}
     if extra is not None and "fp32" in extra:
         kw.update(prec="fp32", ref_rho=1.0, ref_p=p0)
