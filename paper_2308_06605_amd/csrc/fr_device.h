@@ -238,14 +238,16 @@ struct Cfg {
 #ifndef FR_WPE_VOLUME32
 #define FR_WPE_VOLUME32(P) ((P) == 5 || (P) == 7 ? 4 : 0)
 #endif
-// Degrees at which a single-pass fused tail writes the face values by whole face points per
-// thread (each point's line and interpolation weights worked out once for all its values)
-// rather than by (group, face point) items of five sums. Measured per degree (A/B in one call):
-// faster at p = 2 (FP32 +13%, FP64 +5%; taken for p = 0, 1 too, where the points also divide
-// evenly over the threads) and p = 4 (+1%, +2%), at p = 5 and 6 in the FP32 form (+3%, +1%);
-// slower at p = 3 (FP64 -10%, FP32 -2%) and at p = 5 in FP64 (-1%).
-#ifndef FR_TAIL_PER_POINT64
-#define FR_TAIL_PER_POINT64(P) ((P) <= 2 || (P) == 4)
+// How a single-pass fused tail spreads the face values over its threads. FP32 form: whole face
+// points per thread (each point's line and interpolation weights worked out once for all its
+// values) at the degrees listed, else (group, face point) items of five sums. FP64: items of
+// FR_TAIL_GROUPS64 of the four groups (4: whole face points). Measured per degree (A/B in one
+// call): whole points are faster at p = 2 (FP32 +13%, FP64 +5%; taken for p = 0, 1 too, where
+// the points also divide evenly over the threads), p = 4 (+1%, +2%) and at p = 5, 6 in the FP32
+// form (+3%, +1%), slower at p = 3 (FP64 -10%, FP32 -2%) and at p = 5 in FP64 (-1%); FP64 items
+// of two groups at p = 3 were no faster than one (5.78-5.85e9 against 5.80-5.82e9).
+#ifndef FR_TAIL_GROUPS64
+#define FR_TAIL_GROUPS64(P) ((P) <= 2 || (P) == 4 ? 4 : 1)
 #endif
 #ifndef FR_TAIL_PER_POINT32
 #define FR_TAIL_PER_POINT32(P) ((P) <= 2 || (P) == 4 || (P) == 5 || (P) == 6)

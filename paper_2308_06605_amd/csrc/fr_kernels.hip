@@ -617,18 +617,23 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       gradient();
     }
     __syncthreads();
-    if constexpr (FR_TAIL_PER_POINT64(P)) {
-      // whole face points per thread: each point's line and interpolation weights once, then its
-      // 20 values; the same sums as the items below
-      for (int fp = t; act && fp < NF; fp += NS) {
+    // items (groups, face point) of GG of the four groups (group 0 the values, group 1 + ii the
+    // d/dx_ii of the five variables: slot 5 + ii * 5 + v; variable v's sits at
+    // sJ[(v * 3 + ii) * NS]); each item works out its line and interpolation weights once
+    constexpr int GG = FR_TAIL_GROUPS64(P);
+    static_assert(GG == 1 || GG == 2 || GG == 4, "groups per item divide the four groups");
+    if (act) {
+      for (int q = t; q < (4 / GG) * NF; q += NS) {
+        const int gi = q / NF;
         int f, kk, b0, stride;
-        line(fp, f, kk, b0, stride);
+        line(q - gi * NF, f, kk, b0, stride);
         const bool hi = f & 1;
         real cf[N];
 #pragma unroll
         for (int c = 0; c < N; ++c) cf[c] = hi ? ops.lp[c] : ops.lm[c];
 #pragma unroll
-        for (int grp = 0; grp < 4; ++grp) {
+        for (int gg = 0; gg < GG; ++gg) {
+          const int grp = gi * GG + gg;
           real *dst = face + ((e * 6 + f) * 20 + 5 * grp) * NFP + kk;
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
@@ -638,26 +643,6 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
             for (int c = 0; c < N; ++c) acc += cf[c] * src[b0 + c * stride];
             face_store<NFP>(acc, &dst[v * NFP]);
           }
-        }
-      }
-      return;
-    }
-    if (act) {
-      // items (group, face point): group 0 the values, group 1 + ii the d/dx_ii of the five
-      // variables (slot 5 + ii * 5 + v; variable v's sits at sJ[(v * 3 + ii) * NS])
-      for (int q = t; q < 4 * NF; q += NS) {
-        const int grp = q / NF;
-        int f, kk, b0, stride;
-        line(q - grp * NF, f, kk, b0, stride);
-        const bool hi = f & 1;
-        real *dst = face + ((e * 6 + f) * 20 + 5 * grp) * NFP + kk;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const real *src = grp == 0 ? &sU[v * NS] : &sJ[(v * 3 + grp - 1) * NS];
-          real acc = 0;
-#pragma unroll
-          for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * src[b0 + c * stride];
-          face_store<NFP>(acc, &dst[v * NFP]);
         }
       }
     }
