@@ -254,6 +254,16 @@ struct Cfg {
 #endif
 #define FR_WPE_ATTR(w) __attribute__((amdgpu_waves_per_eu((w) > 0 ? (w) : 1, (w) > 0 ? 8 : 8)))
 
+// Whether `extra` more bytes of LDS per block leave the blocks a CU can hold unchanged: a block
+// of `threads` threads using `bytes` of the CU's 160 KB (and at most 32 waves per CU).
+constexpr int lds_blocks(int bytes, int threads) {
+  const int by_lds = (160 * 1024) / bytes, by_waves = 32 / ((threads + 63) / 64);
+  return by_lds < by_waves ? by_lds : by_waves;
+}
+constexpr bool lds_copy_fits(int bytes, int extra, int threads) {
+  return lds_blocks(bytes + extra, threads) == lds_blocks(bytes, threads);
+}
+
 template <typename real>
 struct OpsT {
   real D[kMaxN * kMaxN];

@@ -300,6 +300,20 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
   // reads only the others again from HBM (each thread reads back its own terms: no barrier).
   constexpr int NMS = PRE && VISC && !LDG && kWavePerFace<NFP, EPB> && sizeof(real) == 8 ? 7 : 0;
   __shared__ real sMet[NMS > 0 ? NMS : 1][NMS > 0 ? NS : 1];
+  // Operator entries indexed by a lane's own point (rows of D, the correction derivatives at
+  // the solution points) are read from an LDS copy. From the kernel argument each would be a
+  // vector memory load, and those complete in issue order: one issued after the RK-register
+  // loads waits for HBM. Rows indexed by the wave-uniform plane index stay scalar loads. The
+  // copy is left out where its bytes would cost a block per CU (p = 3, whose blocks fill the
+  // LDS exactly). (Written as conditional expressions: through accessor lambdas the code
+  // without the copy compiled differently and spilled more.)
+  constexpr bool UNI2 = N * N == 64 && EPB == 1;
+  constexpr int LDS0 = (int)sizeof(real) * (EPB * 5 * NS + EPB * NJ + NMS * NS);
+  constexpr bool OPL = lds_copy_fits(LDS0, (int)sizeof(real) * (N * N + 2 * N), EPB * NS);
+  __shared__ real sOp[OPL ? N * N + 2 * N : 1];
+  if (OPL)
+    for (int i = threadIdx.x; i < N * N + 2 * N; i += EPB * NS)
+      sOp[i] = i < N * N ? ops.D[i] : (i < N * N + N ? ops.gcL[i - N * N] : ops.gcR[i - N * N - N]);
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blockIdx.x * EPB + slot;
   const bool act = e < E;
@@ -370,9 +384,9 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
         real d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-          d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-          d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+          d0 += (OPL ? sOp[idx[0] * N + c] : ops.D[idx[0] * N + c]) * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+          d1 += (OPL ? sOp[idx[1] * N + c] : ops.D[idx[1] * N + c]) * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+          d2 += (OPL && !UNI2 ? sOp[idx[2] * N + c] : ops.D[idx[2] * N + c]) * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
         }
         dU[0][v] = d0;
         dU[1][v] = d1;
@@ -382,7 +396,8 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       for (int d = 0; d < 3; ++d) {
         const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
         const int kk = idx[u] + N * idx[w];
-        const real cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+        const bool cpy = OPL && !(UNI2 && d == 2);
+        const real cL = cpy ? sOp[N * N + idx[d]] : ops.gcL[idx[d]], cR = cpy ? sOp[N * N + N + idx[d]] : ops.gcR[idx[d]];
 #pragma unroll
         for (int v = 0; v < 5; ++v)
           dU[d][v] += sJ[(5 + v) * NF + (2 * d) * NFP + kk] * cL + sJ[(5 + v) * NF + (2 * d + 1) * NFP + kk] * cR;
@@ -462,7 +477,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
         for (int c = 0; c < N; ++c) {
           const int id = d == 0 ? c + N * (idx[1] + N * idx[2])
                                 : (d == 1 ? idx[0] + N * (c + N * idx[2]) : idx[0] + N * (idx[1] + N * c));
-          acc += ops.D[idx[d] * N + c] * sF[v * NS + id];
+          acc += (OPL && !(UNI2 && d == 2) ? sOp[idx[d] * N + c] : ops.D[idx[d] * N + c]) * sF[v * NS + id];
         }
         div[v] += acc;
       }
@@ -493,7 +508,8 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
     if (act) {
       const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
       const int kk = idx[u] + N * idx[w];
-      const real cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+      const bool cpy = OPL && !(UNI2 && d == 2);
+      const real cL = cpy ? sOp[N * N + idx[d]] : ops.gcL[idx[d]], cR = cpy ? sOp[N * N + N + idx[d]] : ops.gcR[idx[d]];
 #pragma unroll
       for (int v = 0; v < 5; ++v) div[v] += sJ[v * NF + (2 * d) * NFP + kk] * cL + sJ[v * NF + (2 * d + 1) * NFP + kk] * cR;
     }
@@ -546,9 +562,9 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       real d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-        d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-        d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+        d0 += (OPL ? sOp[idx[0] * N + c] : ops.D[idx[0] * N + c]) * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+        d1 += (OPL ? sOp[idx[1] * N + c] : ops.D[idx[1] * N + c]) * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+        d2 += (OPL && !UNI2 ? sOp[idx[2] * N + c] : ops.D[idx[2] * N + c]) * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
       }
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
@@ -583,9 +599,9 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
               real d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
               for (int c = 0; c < N; ++c) {
-                d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-                d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-                d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+                d0 += (OPL ? sOp[idx[0] * N + c] : ops.D[idx[0] * N + c]) * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+                d1 += (OPL ? sOp[idx[1] * N + c] : ops.D[idx[1] * N + c]) * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+                d2 += (OPL && !UNI2 ? sOp[idx[2] * N + c] : ops.D[idx[2] * N + c]) * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
               }
 #pragma unroll
               for (int ii = 0; ii < 3; ++ii) {
@@ -678,9 +694,9 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
             real d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
             for (int c = 0; c < N; ++c) {
-              d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-              d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-              d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+              d0 += (OPL ? sOp[idx[0] * N + c] : ops.D[idx[0] * N + c]) * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+              d1 += (OPL ? sOp[idx[1] * N + c] : ops.D[idx[1] * N + c]) * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+              d2 += (OPL && !UNI2 ? sOp[idx[2] * N + c] : ops.D[idx[2] * N + c]) * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
             }
 #pragma unroll
             for (int ii = 0; ii < 3; ++ii) {

@@ -403,6 +403,23 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
   // not read that copy from HBM again; each thread reads back its own terms (no barrier).
   constexpr bool MST = PRE && VISC && (P == 3 || P == 7);
   __shared__ float sMetall[EPB][MST ? 10 * NS : 1];
+  // Operator entries indexed by a lane's own point (rows of D, the correction derivatives at
+  // the solution points) come from LDS copies, as in the FP64 volume kernel: from the kernel
+  // argument each would be a vector memory load, which completes in issue order, after the
+  // RK-register loads. Rows indexed by the wave-uniform plane index stay scalar loads; the copies
+  // are left out where their bytes would cost a block per CU. (Conditional expressions rather
+  // than accessor lambdas, which changed the code generated without the copies.)
+  constexpr bool UNI2 = N * N == 64 && EPB == 1;
+  constexpr int NOP = N * N + 2 * N;
+  constexpr int LDS0 = EPB * (4 * 5 * NS + 8 * NMS + 4 * NJ + 8 * NF + (MST ? 4 * 10 * NS : 0));
+  constexpr bool OPL = lds_copy_fits(LDS0, 12 * NOP, EPB * NS);
+  __shared__ float sOpf[OPL ? NOP : 1];
+  __shared__ double sOpd[OPL ? NOP : 1];
+  if (OPL)
+    for (int i = threadIdx.x; i < NOP; i += EPB * NS) {
+      sOpf[i] = i < N * N ? ops.D[i] : (i < N * N + N ? ops.gcL[i - N * N] : ops.gcR[i - N * N - N]);
+      sOpd[i] = i < N * N ? opsd.D[i] : (i < N * N + N ? opsd.gcL[i - N * N] : opsd.gcR[i - N * N - N]);
+    }
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blk * EPB + slot;
   const bool act = e < E;
@@ -471,9 +488,9 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
         float d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-          d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-          d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+          d0 += (OPL ? sOpf[idx[0] * N + c] : ops.D[idx[0] * N + c]) * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+          d1 += (OPL ? sOpf[idx[1] * N + c] : ops.D[idx[1] * N + c]) * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+          d2 += (OPL && !UNI2 ? sOpf[idx[2] * N + c] : ops.D[idx[2] * N + c]) * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
         }
         dU[0][v] = d0;
         dU[1][v] = d1;
@@ -483,7 +500,8 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
       for (int d = 0; d < 3; ++d) {
         const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
         const int kk = idx[u] + N * idx[w];
-        const float cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+        const bool cpy = OPL && !(UNI2 && d == 2);
+        const float cL = cpy ? sOpf[N * N + idx[d]] : ops.gcL[idx[d]], cR = cpy ? sOpf[N * N + N + idx[d]] : ops.gcR[idx[d]];
 #pragma unroll
         for (int v = 0; v < 5; ++v)
           dU[d][v] += sJ[(4 + v) * NF + (2 * d) * NFP + kk] * cL + sJ[(4 + v) * NF + (2 * d + 1) * NFP + kk] * cR;
@@ -552,7 +570,7 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
         for (int c = 0; c < N; ++c) {
           const int id = d == 0 ? c + N * (idx[1] + N * idx[2])
                                 : (d == 1 ? idx[0] + N * (c + N * idx[2]) : idx[0] + N * (idx[1] + N * c));
-          acc += ops.D[idx[d] * N + c] * sF[v * NS + id];
+          acc += (OPL && !(UNI2 && d == 2) ? sOpf[idx[d] * N + c] : ops.D[idx[d] * N + c]) * sF[v * NS + id];
         }
         div[1 + v] += acc;
       }
@@ -562,7 +580,7 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
         for (int c = 0; c < N; ++c) {
           const int id = d == 0 ? c + N * (idx[1] + N * idx[2])
                                 : (d == 1 ? idx[0] + N * (c + N * idx[2]) : idx[0] + N * (idx[1] + N * c));
-          acc += opsd.D[idx[d] * N + c] * sM[id];
+          acc += (OPL && !(UNI2 && d == 2) ? sOpd[idx[d] * N + c] : opsd.D[idx[d] * N + c]) * sM[id];
         }
         divm += acc;
       }
@@ -599,10 +617,11 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
     if (act) {
       const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
       const int kk = idx[u] + N * idx[w];
-      const float cL = ops.gcL[idx[d]], cR = ops.gcR[idx[d]];
+      const bool cpy = OPL && !(UNI2 && d == 2);
+      const float cL = cpy ? sOpf[N * N + idx[d]] : ops.gcL[idx[d]], cR = cpy ? sOpf[N * N + N + idx[d]] : ops.gcR[idx[d]];
 #pragma unroll
       for (int v = 0; v < 4; ++v) div[1 + v] += sJ[v * NF + (2 * d) * NFP + kk] * cL + sJ[v * NF + (2 * d + 1) * NFP + kk] * cR;
-      divm += sJm[(2 * d) * NFP + kk] * opsd.gcL[idx[d]] + sJm[(2 * d + 1) * NFP + kk] * opsd.gcR[idx[d]];
+      divm += sJm[(2 * d) * NFP + kk] * (cpy ? sOpd[N * N + idx[d]] : opsd.gcL[idx[d]]) + sJm[(2 * d + 1) * NFP + kk] * (cpy ? sOpd[N * N + N + idx[d]] : opsd.gcR[idx[d]]);
     }
   }
   // the RK update; with PRE the stored state also goes to LDS at once as U' (nothing reads sU
@@ -663,9 +682,9 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
           float d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
           for (int c = 0; c < N; ++c) {
-            d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-            d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-            d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+            d0 += (OPL ? sOpf[idx[0] * N + c] : ops.D[idx[0] * N + c]) * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+            d1 += (OPL ? sOpf[idx[1] * N + c] : ops.D[idx[1] * N + c]) * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+            d2 += (OPL && !UNI2 ? sOpf[idx[2] * N + c] : ops.D[idx[2] * N + c]) * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
           }
 #pragma unroll
           for (int ii = 0; ii < 3; ++ii) sJ[(v * 3 + ii) * NS + t] = iJb * (jb[ii] * d0 + jb[3 + ii] * d1 + jb[6 + ii] * d2);
@@ -779,9 +798,9 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
             float d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
             for (int c = 0; c < N; ++c) {
-              d0 += ops.D[idx[0] * N + c] * sU[v * NS + c + N * (idx[1] + N * idx[2])];
-              d1 += ops.D[idx[1] * N + c] * sU[v * NS + idx[0] + N * (c + N * idx[2])];
-              d2 += ops.D[idx[2] * N + c] * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
+              d0 += (OPL ? sOpf[idx[0] * N + c] : ops.D[idx[0] * N + c]) * sU[v * NS + c + N * (idx[1] + N * idx[2])];
+              d1 += (OPL ? sOpf[idx[1] * N + c] : ops.D[idx[1] * N + c]) * sU[v * NS + idx[0] + N * (c + N * idx[2])];
+              d2 += (OPL && !UNI2 ? sOpf[idx[2] * N + c] : ops.D[idx[2] * N + c]) * sU[v * NS + idx[0] + N * (idx[1] + N * c)];
             }
 #pragma unroll
             for (int ii = 0; ii < 3; ++ii) sJ[(w * 3 + ii) * NS + t] = iJb * (jb[ii] * d0 + jb[3 + ii] * d1 + jb[6 + ii] * d2);
