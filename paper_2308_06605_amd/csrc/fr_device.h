@@ -252,6 +252,18 @@ struct Cfg {
 #ifndef FR_TAIL_PER_POINT32
 #define FR_TAIL_PER_POINT32(P) ((P) <= 2 || (P) == 4 || (P) == 5 || (P) == 6)
 #endif
+// Degrees at which the kernels make that choice from scalar loads (pick_end); elsewhere the
+// compiler's vector load of a selected address stays. Measured per degree (A/B in one call):
+// FP64 64^3 p=3 +1-2%, 52^3 p=4 +2.5%, 43^3 p=5 +4%, while at 80^3 p=2 the fused volume kernel
+// went from 1.99 to 2.09 ms and at 37^3 p=6 it took 130 VGPRs (a wave per SIMD less); FP32 form
+// 64^3 p=3 +3%, 52^3 p=4 +12%, 43^3 p=5 +11%, 37^3 p=6 +8%, 80^3 p=2 -3%. At p = 7 the choice
+// is made per wave (no difference).
+#ifndef FR_SCALAR_ENDS64
+#define FR_SCALAR_ENDS64(P) ((P) == 3 || (P) == 4 || (P) == 5)
+#endif
+#ifndef FR_SCALAR_ENDS32
+#define FR_SCALAR_ENDS32(P) ((P) >= 3)
+#endif
 #define FR_WPE_ATTR(w) __attribute__((amdgpu_waves_per_eu((w) > 0 ? (w) : 1, (w) > 0 ? 8 : 8)))
 
 // Whether `extra` more bytes of LDS per block leave the blocks a CU can hold unchanged: a block
@@ -262,6 +274,28 @@ constexpr int lds_blocks(int bytes, int threads) {
 }
 constexpr bool lds_copy_fits(int bytes, int extra, int threads) {
   return lds_blocks(bytes + extra, threads) == lds_blocks(bytes, threads);
+}
+
+// An operator entry at a uniform index, chosen per lane between two tables (the interpolation
+// to the face at -1 or at +1). As a select of the two values the compiler makes it one vector
+// load from a selected address, and a vector load completes only after every vector memory
+// access the wave issued before it (the RK-register loads, the stores of earlier face points).
+// Passing both through readfirstlane keeps them scalar loads and the choice a register select.
+template <typename T>
+__device__ __forceinline__ T uniform_value(T x) {
+  if constexpr (sizeof(T) == 8) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+  }
+}
+template <bool SCALAR, typename T>
+__device__ __forceinline__ T pick_end(bool hi, const T *lm, const T *lp, int c) {
+  if constexpr (SCALAR) return hi ? uniform_value(lp[c]) : uniform_value(lm[c]);
+  else return hi ? lp[c] : lm[c];
 }
 
 template <typename real>

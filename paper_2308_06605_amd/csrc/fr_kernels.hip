@@ -108,7 +108,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) v
     const int grp = q / NF, fp = q - grp * NF;
     const int f = fp / NFP, kk = fp - f * NFP;
     const int a = kk % N, b = kk / N, d = f >> 1;
-    const real *ell = (f & 1) ? ops.lp : ops.lm;
+    const bool hi = f & 1;
     real *dst = face + ((e * 6 + f) * 20 + GV * grp) * NFP + kk;
 #pragma unroll
     for (int v = 0; v < GV; ++v) {
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_PREPASS(P)) v
       const real *src = val < 5 ? &sU[slot][val][0] : &sG[slot][(val - 5) % (NG > 0 ? NG : 1)][0];
       real acc = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) acc += ell[c] * src[line_pt<N>(d, c, a, b)];
+      for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS64(P)>(hi, ops.lm, ops.lp, c) * src[line_pt<N>(d, c, a, b)];
       face_store<NFP>(acc, &dst[v * NFP]);
     }
   }
@@ -440,6 +440,12 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       for (int d = 0; d < 3; ++d) F[d][v] = ja[d * 3 + 0] * f0 + ja[d * 3 + 1] * f1 + ja[d * 3 + 2] * f2;
     }
   }
+  // Without room for that copy, the viscous kernel keeps one for the divergence phase in slot
+  // 0's jump entries, which nothing reads after the gradient phase. It is stored after the
+  // phase's first barrier, each thread picking its entry out of the whole table read by scalar
+  // loads (which do not wait for the vector loads of the RK registers).
+  constexpr int NOP = N * N + 2 * N;
+  constexpr bool OPX = !OPL && VISC && 5 * NF + NOP <= NJ;
   // the RK registers are loaded here so that their latency overlaps the divergence phase
   if (act) {
     // (assigned per mode, not initialised up front: a live range from the kernel's start
@@ -461,12 +467,20 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
   // divergence of the transformed flux and the flux correction, one direction at a time
   real div[5] = {0, 0, 0, 0, 0};
   real *sF = sU;
+  real *sOpx = &sJall[0][5 * NF];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     __syncthreads();
     if (act) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) sF[v * NS + t] = F[d][v];
+    }
+    if (OPX && d == 0 && threadIdx.x < NOP) {
+      real opv = 0;
+#pragma unroll
+      for (int i = 0; i < NOP; ++i)
+        if ((int)threadIdx.x == i) opv = i < N * N ? ops.D[i] : (i < N * N + N ? ops.gcL[i - N * N] : ops.gcR[i - N * N - N]);
+      sOpx[threadIdx.x] = opv;
     }
     __syncthreads();
     if (act) {
@@ -477,7 +491,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
         for (int c = 0; c < N; ++c) {
           const int id = d == 0 ? c + N * (idx[1] + N * idx[2])
                                 : (d == 1 ? idx[0] + N * (c + N * idx[2]) : idx[0] + N * (idx[1] + N * c));
-          acc += (OPL && !(UNI2 && d == 2) ? sOp[idx[d] * N + c] : ops.D[idx[d] * N + c]) * sF[v * NS + id];
+          acc += (OPL && !(UNI2 && d == 2) ? sOp[idx[d] * N + c] : (OPX ? sOpx[idx[d] * N + c] : ops.D[idx[d] * N + c])) * sF[v * NS + id];
         }
         div[v] += acc;
       }
@@ -493,12 +507,12 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
         for (int fp = t; fp < 2 * NFP; fp += NS) {
           const int f = 2 * d + fp / NFP, kk = fp % NFP;
           const int a = kk % N, b = kk / N;
-          const real *ell = (f & 1) ? ops.lp : ops.lm;
+          const bool hi = f & 1;
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
             real acc = 0;
 #pragma unroll
-            for (int c = 0; c < N; ++c) acc += ell[c] * sF[v * NS + line_pt<N>(d, c, a, b)];
+            for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS64(P)>(hi, ops.lm, ops.lp, c) * sF[v * NS + line_pt<N>(d, c, a, b)];
             sJ[v * NF + f * NFP + kk] -= acc;
           }
         }
@@ -509,7 +523,8 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       const int u = d == 0 ? 1 : 0, w = d == 2 ? 1 : 2;
       const int kk = idx[u] + N * idx[w];
       const bool cpy = OPL && !(UNI2 && d == 2);
-      const real cL = cpy ? sOp[N * N + idx[d]] : ops.gcL[idx[d]], cR = cpy ? sOp[N * N + N + idx[d]] : ops.gcR[idx[d]];
+      const real cL = cpy ? sOp[N * N + idx[d]] : (OPX ? sOpx[N * N + idx[d]] : ops.gcL[idx[d]]);
+      const real cR = cpy ? sOp[N * N + N + idx[d]] : (OPX ? sOpx[N * N + N + idx[d]] : ops.gcR[idx[d]]);
 #pragma unroll
       for (int v = 0; v < 5; ++v) div[v] += sJ[v * NF + (2 * d) * NFP + kk] * cL + sJ[v * NF + (2 * d + 1) * NFP + kk] * cR;
     }
@@ -646,7 +661,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
         const bool hi = f & 1;
         real cf[N];
 #pragma unroll
-        for (int c = 0; c < N; ++c) cf[c] = hi ? ops.lp[c] : ops.lm[c];
+        for (int c = 0; c < N; ++c) cf[c] = pick_end<FR_SCALAR_ENDS64(P)>(hi, ops.lm, ops.lp, c);
 #pragma unroll
         for (int gg = 0; gg < GG; ++gg) {
           const int grp = gi * GG + gg;
@@ -674,7 +689,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
       const bool hi = f & 1;
       real acc = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sU[v * NS + b0 + c * stride];
+      for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS64(P)>(hi, ops.lm, ops.lp, c) * sU[v * NS + b0 + c * stride];
       face_store<NFP>(acc, &face[((e * 6 + f) * 20 + v) * NFP + kk]);
     }
   }
@@ -718,7 +733,7 @@ __global__ __launch_bounds__(EPBX * Cfg<P>::NS) FR_WPE_ATTR(FR_WPE_VOLUME(P, SGS
           const bool hi = f & 1;
           real acc = 0;
 #pragma unroll
-          for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sJ[ci * NS + b0 + c * stride];
+          for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS64(P)>(hi, ops.lm, ops.lp, c) * sJ[ci * NS + b0 + c * stride];
           face_store<NFP>(acc, &face[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
         }
       }

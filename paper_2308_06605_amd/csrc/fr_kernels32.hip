@@ -197,8 +197,14 @@ __device__ __forceinline__ void prepass32_body(unsigned blk, const double *__res
   for (int fp = t; fp < NF; fp += NS) {
     const int f = fp / NFP, kk = fp - f * NFP;
     const int a = kk % N, b = kk / N, d = f >> 1;
-    const float *ell = (f & 1) ? ops.lp : ops.lm;
-    const double *elld = (f & 1) ? opsd.lp : opsd.lm;
+    const bool hi = f & 1;
+    float ell[N];
+    double elld[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      ell[c] = pick_end<FR_SCALAR_ENDS32(P)>(hi, ops.lm, ops.lp, c);
+      elld[c] = pick_end<FR_SCALAR_ENDS32(P)>(hi, opsd.lm, opsd.lp, c);
+    }
     float *dst = face32 + ((e * 6 + f) * 20) * NFP + kk;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -598,18 +604,17 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
       for (int fp = t; fp < 2 * NFP; fp += NS) {
         const int f = 2 * d + fp / NFP, kk = fp % NFP;
         const int a = kk % N, b = kk / N;
-        const float *ell = (f & 1) ? ops.lp : ops.lm;
-        const double *elld = (f & 1) ? opsd.lp : opsd.lm;
+        const bool hi = f & 1;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float acc = 0;
 #pragma unroll
-          for (int c = 0; c < N; ++c) acc += ell[c] * sF[v * NS + line_pt<N>(d, c, a, b)];
+          for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS32(P)>(hi, ops.lm, ops.lp, c) * sF[v * NS + line_pt<N>(d, c, a, b)];
           sJ[v * NF + f * NFP + kk] -= acc;
         }
         double acc = 0;
 #pragma unroll
-        for (int c = 0; c < N; ++c) acc += elld[c] * sM[line_pt<N>(d, c, a, b)];
+        for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS32(P)>(hi, opsd.lm, opsd.lp, c) * sM[line_pt<N>(d, c, a, b)];
         sJm[f * NFP + kk] -= acc;
       }
     }
@@ -703,8 +708,8 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
         double cd[N];
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-          cf[c] = hi ? ops.lp[c] : ops.lm[c];
-          cd[c] = hi ? opsd.lp[c] : opsd.lm[c];
+          cf[c] = pick_end<FR_SCALAR_ENDS32(P)>(hi, ops.lm, ops.lp, c);
+          cd[c] = pick_end<FR_SCALAR_ENDS32(P)>(hi, opsd.lm, opsd.lp, c);
         }
 #pragma unroll
         for (int grp = 0; grp < NGRP - 1; ++grp) {
@@ -738,7 +743,7 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
           for (int i = 0; i < 3; ++i) {
             double acc = 0;
 #pragma unroll
-            for (int c = 0; c < N; ++c) acc += (hi ? opsd.lp[c] : opsd.lm[c]) * sM[i * NS + b0 + c * stride];
+            for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS32(P)>(hi, opsd.lm, opsd.lp, c) * sM[i * NS + b0 + c * stride];
             face_store<NFP>(acc, &facem[((e * 6 + f) * 3 + i) * NFP + kk]);
           }
         } else {
@@ -747,7 +752,7 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
             const float *src = grp == 0 ? &sU[v * NS] : &sJ[(v * 3 + grp - 1) * NS];
             float acc = 0;
 #pragma unroll
-            for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * src[b0 + c * stride];
+            for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS32(P)>(hi, ops.lm, ops.lp, c) * src[b0 + c * stride];
             face_store<NFP>(acc, &face32[((e * 6 + f) * 20 + 5 * grp + v) * NFP + kk]);
           }
         }
@@ -774,7 +779,7 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
       const bool hi = f & 1;
       float acc = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sU[v * NS + b0 + c * stride];
+      for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS32(P)>(hi, ops.lm, ops.lp, c) * sU[v * NS + b0 + c * stride];
       face_store<NFP>(acc, &face32[((e * 6 + f) * 20 + v) * NFP + kk]);
     }
   }
@@ -831,7 +836,7 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
           const bool hi = f & 1;
           double acc = 0;
 #pragma unroll
-          for (int c = 0; c < N; ++c) acc += (hi ? opsd.lp[c] : opsd.lm[c]) * sM[b0 + c * stride];
+          for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS32(P)>(hi, opsd.lm, opsd.lp, c) * sM[b0 + c * stride];
           face_store<NFP>(acc, &facem[((e * 6 + f) * 3 + r) * NFP + kk]);
         }
       }
@@ -843,7 +848,7 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
         const bool hi = f & 1;
         float acc = 0;
 #pragma unroll
-        for (int c = 0; c < N; ++c) acc += (hi ? ops.lp[c] : ops.lm[c]) * sJ[ci * NS + b0 + c * stride];
+        for (int c = 0; c < N; ++c) acc += pick_end<FR_SCALAR_ENDS32(P)>(hi, ops.lm, ops.lp, c) * sJ[ci * NS + b0 + c * stride];
         face_store<NFP>(acc, &face32[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + kk]);
       }
     }
