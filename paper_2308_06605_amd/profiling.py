@@ -136,16 +136,27 @@ def per_kernel_kib(path: str, counter: str):
     return {key: sum(v) / len(v) for key, v in vals.items()}
 
 
+def last_copy_kib(path: str, counter: str) -> float:
+    """The counter of the run's last device copy: the calibration copy bench.py makes after
+    everything else (other copies, such as state uploads and the copy-bandwidth measurement, share
+    its kernel and grid size, so it is told apart by dispatch order)."""
+    last = None
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]:
+                d = int(r["Dispatch_Id"])
+                if last is None or d > last[0]:
+                    last = (d, float(r["Counter_Value"]))
+    if last is None:
+        raise SystemExit("no calibration copy dispatch found")
+    return last[1]
+
+
 def summarize(fetch_csv: str, write_csv: str, calib_bytes: int, prec: str = "fp64") -> dict:
     fetch = per_kernel_kib(fetch_csv, "FETCH_SIZE")
     write = per_kernel_kib(write_csv, "WRITE_SIZE")
-    # the calibration copy: the copy dispatch with the largest write
-    copies = [k for k in write if "copyBuffer" in k[0]]
-    if not copies:
-        raise SystemExit("no calibration copy dispatch found")
-    cal = max(copies, key=lambda k: write[k])
-    f_scale = calib_bytes / 1024.0 / fetch[cal]
-    w_scale = calib_bytes / 1024.0 / write[cal]
+    f_scale = calib_bytes / 1024.0 / last_copy_kib(fetch_csv, "FETCH_SIZE")
+    w_scale = calib_bytes / 1024.0 / last_copy_kib(write_csv, "WRITE_SIZE")
     kernels = {}
     for key in fetch:
         name = key[0]
@@ -256,11 +267,12 @@ def stage_markdown(stats_csv: str, traffic_json: str, n: int, p: int, prec: str,
         rd, wr = (k["fetch_bytes"] / 1e9, k["write_bytes"] / 1e9) if k else (float("nan"), float("nan"))
         lines.append(f"| {name} | {calls} | {avg:.4f} | {mn:.4f} | {mx:.4f} | {alg:.3f} | {rd:.3f} + {wr:.3f} | "
                      f"{alg / avg * 1e3:.0f} | {(rd + wr) / avg * 1e3:.0f} |")
-    face, vol = kinds["face"], kinds["volume_pre"]
-    if face in st and vol in st:
-        t = st[face][1] + st[vol][1]
+    # a stage: the face kernel and the fused volume kernel, or without fusion the three kernels
+    parts = [kinds["face"], kinds["volume_pre"]] if fuse else [kinds["prepass"], kinds["face"], kinds["volume"]]
+    if all(k in st for k in parts):
+        t = sum(st[k][1] for k in parts)
         smin = ab["stage_min"] * E
-        lines += ["", f"Stage ({face} + {vol}): {t:.4f} ms, {n ** 3 * (p + 1) ** 3 / (t * 1e-3):.4g} DOF-updates/s; "
+        lines += ["", f"Stage ({' + '.join(parts)}): {t:.4f} ms, {n ** 3 * (p + 1) ** 3 / (t * 1e-3):.4g} DOF-updates/s; "
                   f"two-pass minimum {smin / 1e9:.3f} GB per stage, {smin / (t * 1e-3) / 1e9:.0f} GB/s, "
                   f"{smin / (t * 1e-3) / 8e12:.3f} of 8 TB/s."]
     return "\n".join(lines) + "\n"

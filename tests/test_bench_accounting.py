@@ -75,3 +75,28 @@ def test_affine_two_pass_minimum():
     assert bench.algorithmic_bytes(7, "fp64", affine=True)["stage_min"] / 512 == 440.0
     assert {k: v for k, v in a3.items() if k != "stage_min"} == {k: v for k, v in c3.items() if k != "stage_min"}
     assert bench.algorithmic_bytes(3, "fp32", affine=True)["stage_min"] / 64 == 440.0
+
+
+def test_calibration_copy_is_the_last_copy(tmp_path):
+    """The counters are scaled by the run's last device copy (the calibration copy), not by an
+    average over every copy that shares its kernel and grid size."""
+    from paper_2308_06605_amd.profiling import summarize
+
+    head = ('"Correlation_Id","Dispatch_Id","Agent_Id","Queue_Id","Process_Id","Thread_Id","Grid_Size",'
+            '"Kernel_Id","Kernel_Name","Workgroup_Size","LDS_Block_Size","Scratch_Size","VGPR_Count",'
+            '"Accum_VGPR_Count","SGPR_Count","Counter_Name","Counter_Value","Start_Timestamp","End_Timestamp"\n')
+
+    def row(d, name, counter, kib):
+        return f'{d},{d},"Agent 1",1,1,1,65536,1,"{name}",256,0,0,8,0,16,"{counter}",{kib},0,1\n'
+
+    paths = {}
+    for counter, copy_kib, kern_kib in (("FETCH_SIZE", 131072.0, 1000.0), ("WRITE_SIZE", 262144.0, 500.0)):
+        p = tmp_path / f"{counter}.csv"
+        p.write_text(head + row(1, "__amd_rocclr_copyBuffer", counter, 4 * copy_kib)
+                     + row(2, "void k_face<3, double, true, false, false, 256>(int)", counter, kern_kib)
+                     + row(3, "__amd_rocclr_copyBuffer", counter, copy_kib))
+        paths[counter] = str(p)
+    s = summarize(paths["FETCH_SIZE"], paths["WRITE_SIZE"], 256 << 20)
+    assert s["fetch_scale"] == pytest.approx(2.0) and s["write_scale"] == pytest.approx(1.0)
+    assert s["kernels"]["k_face"]["fetch_bytes"] == pytest.approx(2000.0 * 1024)
+    assert s["kernels"]["k_face"]["write_bytes"] == pytest.approx(500.0 * 1024)
