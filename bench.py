@@ -346,7 +346,8 @@ def main():
                    "p": args.p, "tiles": main_run["tiles"], "stages_per_step": STAGES[args.scheme],
                    "parallelism": "single GPU"},
         "roofline": main_run["roofline"],
-        "stage": {k: main_run[k] for k in ("stage_ms", "kernel_ms", "kernel_gbs")},
+        "stage": {k: main_run[k] for k in ("stage_ms", "kernel_ms", "kernel_gbs", "repeats_ms_per_step",
+                                           "median_value", "residual_ms")},
         "variants": variants,
         "cpu_baseline": cpu,
         "setup_s": main_run["setup_s"],
