@@ -331,18 +331,39 @@ __device__ __forceinline__ int plane_index(int t) {
   else return t / (N * N);
 }
 
-// Face interpolation of a point-ordered element array src: sum over c = 0..N-1, in ascending
-// order, of ell[c] src[line_pt(d, c, a, b)], the line normal to face f (direction d = f/2) through
-// its face point (a, b), with ell = l(-1) or l(+1) by the face's side. f must be the same on every
-// lane of the wavefront (the p = 7 kernels give each wavefront one face of 64 points): the
-// direction then picks one of three loops whose LDS strides are constants, and ell is read
-// through scalar loads. The sums are those of the per-lane form, term for term.
-template <int N, typename T, typename C>
-__device__ __forceinline__ T face_sum_uniform(int f, int a, int b, const T *src, const C *lm, const C *lp) {
+// Face interpolation of a point-ordered element array src: the sum over the line normal to
+// face f (direction d = f/2) through its face point (a, b) of ell[c] src[line_pt(d, c, a, b)],
+// with ell = l(-1) or l(+1) by the face's side. f must be the same on every lane of the
+// wavefront (the p = 7 kernels give each wavefront one face of 64 points): the direction then
+// picks one of three loops whose LDS strides are constants.
+// * In ascending c (ROT false, and faces normal to xi_2 always) ell is read through scalar
+//   loads. On faces normal to xi_0 and xi_1 the lines' common stride (8 or 64 entries) then puts
+//   8 lanes of a wavefront on one LDS bank at every step (16 for doubles): an 8-way conflict.
+// * With ROT, lane (a, b) of those faces starts at c = r and wraps around (r = b + (a & 4) for
+//   xi_0, b for xi_1, mod 8): every step then reads 64 different banks for floats, and 32
+//   different 8-byte bank pairs per half-wavefront for doubles. The weights of the rotated order
+//   come from rot, an LDS table [l(-1), l(-1), l(+1), l(+1)] (rot_entry) where they are
+//   contiguous.
+// A form's kernels all take the same ROT, so fused and separate stages keep the same sums.
+template <int N, typename C>
+__device__ __forceinline__ C rot_entry(const C *lm, const C *lp, int i) {
+  return i < 2 * N ? lm[i % N] : lp[i % N];
+}
+template <int N, bool ROT = false, typename T, typename C>
+__device__ __forceinline__ T face_sum_uniform(int f, int a, int b, const T *src, const C *lm, const C *lp,
+                                              const C *rot = nullptr) {
+  constexpr bool R = ROT && N == 8;  // the rotation is worked out for lines of eight points
   const C *ell = (f & 1) ? lp : lm;
   const int d = f >> 1;
   T acc = 0;
-  if (d == 0) {
+  if (R && d < 2) {
+    const int r = (d == 0 ? b + (a & 4) : b) & (N - 1);
+    const C *w = rot + ((f & 1) ? 2 * N : 0) + r;
+    const T *q = d == 0 ? src + N * (a + N * b) : src + a + N * N * b;
+    const int st = d == 0 ? 1 : N;
+#pragma unroll
+    for (int s = 0; s < N; ++s) acc += w[s] * q[((s + r) & (N - 1)) * st];
+  } else if (d == 0) {
     const T *q = src + N * (a + N * b);
 #pragma unroll
     for (int c = 0; c < N; ++c) acc += ell[c] * q[c];

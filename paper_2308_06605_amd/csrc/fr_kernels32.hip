@@ -138,6 +138,14 @@ __device__ __forceinline__ void prepass32_body(unsigned blk, const double *__res
   __shared__ float sU[EPB][5][NS];
   __shared__ double sM[EPB][3][NS];
   __shared__ float sG[EPB][NG][NS];
+  constexpr bool WPF = kWavePerFace<NFP, EPB>;
+  __shared__ float sRot[WPF ? 4 * N : 1];  // the rotated face sums' weights, FP32 and FP64
+  __shared__ double sRotd[WPF ? 4 * N : 1];
+  if (WPF)
+    for (int i = threadIdx.x; i < 4 * N; i += EPB * NS) {
+      sRot[i] = rot_entry<N>(ops.lm, ops.lp, i);
+      sRotd[i] = rot_entry<N>(opsd.lm, opsd.lp, i);
+    }
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blk * EPB + slot;
   const bool act = e < E;
@@ -184,11 +192,11 @@ __device__ __forceinline__ void prepass32_body(unsigned blk, const double *__res
       const int val = k / 6, f = k - 6 * val;
       if (val < NV) {
         const float *src = val < 5 ? &sU[slot][val][0] : &sG[slot][(val - 5) % NG][0];
-        face_store<NFP>(face_sum_uniform<N>(f, a, b, src, ops.lm, ops.lp),
+        face_store<NFP>(face_sum_uniform<N, true>(f, a, b, src, ops.lm, ops.lp, sRot),
                         &face32[((e * 6 + f) * 20 + val) * NFP + lane]);
       } else {
         const int i = val - NV;
-        face_store<NFP>(face_sum_uniform<N>(f, a, b, &sM[slot][i][0], opsd.lm, opsd.lp),
+        face_store<NFP>(face_sum_uniform<N, true>(f, a, b, &sM[slot][i][0], opsd.lm, opsd.lp, sRotd),
                         &facem[((e * 6 + f) * 3 + i) * NFP + lane]);
       }
     }
@@ -425,6 +433,14 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
     for (int i = threadIdx.x; i < NOP; i += EPB * NS) {
       sOpf[i] = i < N * N ? ops.D[i] : (i < N * N + N ? ops.gcL[i - N * N] : ops.gcR[i - N * N - N]);
       sOpd[i] = i < N * N ? opsd.D[i] : (i < N * N + N ? opsd.gcL[i - N * N] : opsd.gcR[i - N * N - N]);
+    }
+  constexpr bool WPF = kWavePerFace<NFP, EPB>;
+  __shared__ float sRot[WPF ? 4 * N : 1];  // the rotated face sums' weights, FP32 and FP64
+  __shared__ double sRotd[WPF ? 4 * N : 1];
+  if (WPF)
+    for (int i = threadIdx.x; i < 4 * N; i += EPB * NS) {
+      sRot[i] = rot_entry<N>(ops.lm, ops.lp, i);
+      sRotd[i] = rot_entry<N>(opsd.lm, opsd.lp, i);
     }
   const int slot = threadIdx.x / NS, t = threadIdx.x - slot * NS;
   const int64_t e = (int64_t)blk * EPB + slot;
@@ -761,14 +777,13 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
     return;
   }
   // p = 7: the face loops as wave-uniform tasks (value, face), 64 face points per task
-  constexpr bool WPF = kWavePerFace<NFP, EPB>;
   const int lane = t & 63, wv = WPF ? __builtin_amdgcn_readfirstlane(t >> 6) : 0;
   const int la = lane % N, lb = lane / N;
   if (act) {
     if constexpr (WPF) {
       for (int k = wv; k < 5 * 6; k += NS / 64) {
         const int v = k / 6, f = k - 6 * v;
-        face_store<NFP>(face_sum_uniform<N>(f, la, lb, &sU[v * NS], ops.lm, ops.lp),
+        face_store<NFP>(face_sum_uniform<N, true>(f, la, lb, &sU[v * NS], ops.lm, ops.lp, sRot),
                         &face32[((e * 6 + f) * 20 + v) * NFP + lane]);
       }
     } else
@@ -817,14 +832,14 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
     if (act && WPF) {
       for (int k = wv; k < (r < 3 ? 6 : 0) + 3 * nv * 6; k += NS / 64) {
         if (r < 3 && k < 6) {
-          face_store<NFP>(face_sum_uniform<N>(k, la, lb, sM, opsd.lm, opsd.lp),
+          face_store<NFP>(face_sum_uniform<N, true>(k, la, lb, sM, opsd.lm, opsd.lp, sRotd),
                           &facem[((e * 6 + k) * 3 + r) * NFP + lane]);
           continue;
         }
         const int kg = r < 3 ? k - 6 : k;
         const int ci = kg / 6, f = kg - 6 * ci;
         const int v = v0 + ci / 3, ii = ci - (ci / 3) * 3;
-        face_store<NFP>(face_sum_uniform<N>(f, la, lb, &sJ[ci * NS], ops.lm, ops.lp),
+        face_store<NFP>(face_sum_uniform<N, true>(f, la, lb, &sJ[ci * NS], ops.lm, ops.lp, sRot),
                         &face32[((e * 6 + f) * 20 + 5 + ii * 5 + v) * NFP + lane]);
       }
     }
