@@ -344,7 +344,11 @@ __device__ __forceinline__ int plane_index(int t) {
 //   different 8-byte bank pairs per half-wavefront for doubles. The weights of the rotated order
 //   come from rot, an LDS table [l(-1), l(-1), l(+1), l(+1)] (rot_entry) where they are
 //   contiguous.
-// A form's kernels all take the same ROT, so fused and separate stages keep the same sums.
+// A form's kernels all take the same ROT, so fused and separate stages keep the same sums. The
+// FP32 form's p = 7 kernels take it (32^3: the pre-pass, at 6.5 conflict cycles per LDS
+// instruction, went from 0.66 to 0.56 ms); the FP64 ones do not: there the rotated sums cost
+// the fused volume kernel more than they saved (1.74 -> 1.80 ms), and their table would cost
+// the pre-pass, whose two blocks fill the LDS exactly, one of them.
 template <int N, typename C>
 __device__ __forceinline__ C rot_entry(const C *lm, const C *lp, int i) {
   return i < 2 * N ? lm[i % N] : lp[i % N];
