@@ -339,11 +339,12 @@ __device__ __forceinline__ int plane_index(int t) {
 // * In ascending c (ROT false, and faces normal to xi_2 always) ell is read through scalar
 //   loads. On faces normal to xi_0 and xi_1 the lines' common stride (8 or 64 entries) then puts
 //   8 lanes of a wavefront on one LDS bank at every step (16 for doubles): an 8-way conflict.
-// * With ROT, lane (a, b) of those faces starts at c = r and wraps around (r = b + (a & 4) for
-//   xi_0, b for xi_1, mod 8): every step then reads 64 different banks for floats, and 32
-//   different 8-byte bank pairs per half-wavefront for doubles. The weights of the rotated order
-//   come from rot, an LDS table [l(-1), l(-1), l(+1), l(+1)] (rot_entry) where they are
-//   contiguous.
+// * With ROT, a lane of a face normal to xi_0 reads its whole line (contiguous) with 16-byte
+//   loads, two for floats and four for doubles, and sums it in ascending c; src must then be
+//   16-byte aligned. On faces normal to xi_1 lane (a, b) starts at c = b and wraps around
+//   (mod 8): every step then reads 64 different banks for floats, and 32 different 8-byte bank
+//   pairs per half-wavefront for doubles. The weights of the rotated order come from rot, an
+//   LDS table [l(-1), l(-1), l(+1), l(+1)] (rot_entry) where they are contiguous.
 // A form's kernels all take the same ROT, so fused and separate stages keep the same sums. The
 // FP32 form's p = 7 kernels take it (32^3: the pre-pass, at 6.5 conflict cycles per LDS
 // instruction, went from 0.66 to 0.56 ms); the FP64 ones do not: there the rotated sums cost
@@ -360,13 +361,22 @@ __device__ __forceinline__ T face_sum_uniform(int f, int a, int b, const T *src,
   const C *ell = (f & 1) ? lp : lm;
   const int d = f >> 1;
   T acc = 0;
-  if (R && d < 2) {
-    const int r = (d == 0 ? b + (a & 4) : b) & (N - 1);
-    const C *w = rot + ((f & 1) ? 2 * N : 0) + r;
-    const T *q = d == 0 ? src + N * (a + N * b) : src + a + N * N * b;
-    const int st = d == 0 ? 1 : N;
+  if (R && d == 0) {
+    constexpr int K = 16 / (int)sizeof(T);
+    using V = T __attribute__((ext_vector_type(K)));
+    const V *q = reinterpret_cast<const V *>(src + N * (a + N * b));
 #pragma unroll
-    for (int s = 0; s < N; ++s) acc += w[s] * q[((s + r) & (N - 1)) * st];
+    for (int j = 0; j < N / K; ++j) {
+      const V x = q[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc += ell[j * K + k] * x[k];
+    }
+  } else if (R && d == 1) {
+    const int r = b & (N - 1);
+    const C *w = rot + ((f & 1) ? 2 * N : 0) + r;
+    const T *q = src + a + N * N * b;
+#pragma unroll
+    for (int s = 0; s < N; ++s) acc += w[s] * q[((s + r) & (N - 1)) * N];
   } else if (d == 0) {
     const T *q = src + N * (a + N * b);
 #pragma unroll

@@ -135,9 +135,10 @@ __device__ __forceinline__ void prepass32_body(unsigned blk, const double *__res
   using C = Cfg<P>;
   constexpr int N = C::N, NS = C::NS, NFP = C::NFP, NF = C::NF, EPB = EPBX;
   constexpr int NG = VISC ? 15 : 1;
-  __shared__ float sU[EPB][5][NS];
-  __shared__ double sM[EPB][3][NS];
-  __shared__ float sG[EPB][NG][NS];
+  // (16-byte aligned: the p = 7 face sums read whole lines with 16-byte loads)
+  __shared__ alignas(16) float sU[EPB][5][NS];
+  __shared__ alignas(16) double sM[EPB][3][NS];
+  __shared__ alignas(16) float sG[EPB][NG][NS];
   constexpr bool WPF = kWavePerFace<NFP, EPB>;
   __shared__ float sRot[WPF ? 4 * N : 1];  // the rotated face sums' weights, FP32 and FP64
   __shared__ double sRotd[WPF ? 4 * N : 1];
@@ -407,9 +408,10 @@ __device__ __forceinline__ void volume32_body(unsigned blk,
   constexpr int NJ0 = (VISC ? 9 : 4) * NF;  // [4][NF] flux (mom 3, reduced energy), [5][NF] jumps
   constexpr int NJ = SP && VISC && 15 * NS > NJ0 ? 15 * NS : NJ0;
   constexpr int NMS = SP ? 3 * NS : NS;
-  __shared__ float sUall[EPB][5 * NS];     // U', later 4 components of the transformed flux
-  __shared__ double sMall[EPB][NMS];       // transformed mass flux of one direction
-  __shared__ float sJall[EPB][NJ];
+  // (16-byte aligned: the p = 7 face sums read whole lines with 16-byte loads)
+  __shared__ alignas(16) float sUall[EPB][5 * NS];  // U', later 4 components of the transformed flux
+  __shared__ alignas(16) double sMall[EPB][NMS];    // transformed mass flux of one direction
+  __shared__ alignas(16) float sJall[EPB][NJ];
   __shared__ double sJmall[EPB][NF];       // mass flux along +xi_d, then its jump
   // With the fused pre-pass at p = 3 and p = 7 the LDS left free at these kernels' occupancy
   // (four blocks of four waves, two of eight) keeps the FP32 metric terms each thread converts
