@@ -244,13 +244,15 @@ struct Cfg {
 // FR_TAIL_GROUPS64 of the four groups (4: whole face points). Measured per degree (A/B in one
 // call): whole points are faster at p = 2 (FP32 +13%, FP64 +5%; taken for p = 0, 1 too, where
 // the points also divide evenly over the threads), p = 4 (+1%, +2%) and at p = 5, 6 in the FP32
-// form (+3%, +1%), slower at p = 3 (FP64 -10%, FP32 -2%) and at p = 5 in FP64 (-1%); FP64 items
-// of two groups at p = 3 were no faster than one (5.78-5.85e9 against 5.80-5.82e9).
+// form (+3%, +1%), slower at p = 3 in FP64 (-10%; items of two groups were no faster than one,
+// 5.78-5.85e9 against 5.80-5.82e9, nor whole points after the operator reads moved to LDS and
+// scalar loads, 5.87e9 against 5.92e9) and at p = 5 in FP64 (-1%). In the FP32 form at p = 3
+// whole points were 2% slower at first and 6% faster after those changes (7.89e9 -> 8.36e9).
 #ifndef FR_TAIL_GROUPS64
 #define FR_TAIL_GROUPS64(P) ((P) <= 2 || (P) == 4 ? 4 : 1)
 #endif
 #ifndef FR_TAIL_PER_POINT32
-#define FR_TAIL_PER_POINT32(P) ((P) <= 2 || (P) == 4 || (P) == 5 || (P) == 6)
+#define FR_TAIL_PER_POINT32(P) ((P) <= 6)
 #endif
 // Degrees at which the kernels make that choice from scalar loads (pick_end); elsewhere the
 // compiler's vector load of a selected address stays. Measured per degree (A/B in one call):
