@@ -100,3 +100,31 @@ def test_calibration_copy_is_the_last_copy(tmp_path):
     assert s["fetch_scale"] == pytest.approx(2.0) and s["write_scale"] == pytest.approx(1.0)
     assert s["kernels"]["k_face"]["fetch_bytes"] == pytest.approx(2000.0 * 1024)
     assert s["kernels"]["k_face"]["write_bytes"] == pytest.approx(500.0 * 1024)
+
+
+def test_stage_line_fused_and_unfused(tmp_path):
+    """The stage summary's stage time: face + fused volume kernel with fusion, pre-pass + face +
+    volume kernel without (the FP32 p=7 stage the autotuner picks)."""
+    import json
+
+    from paper_2308_06605_amd.profiling import algorithmic_bytes, kernel_source_hash, stage_markdown
+
+    stats = tmp_path / "kernel_stats.csv"
+    rows = [("void (anonymous namespace)::k_prepass32<7, true, 1>(int)", 0.5),
+            ("void (anonymous namespace)::k_face32<7, true, 64>(int)", 0.3),
+            ("void (anonymous namespace)::k_volume32<7, true, 1, false>(int)", 0.8),
+            ("void (anonymous namespace)::k_volume32<7, true, 1, true>(int)", 1.4)]
+    stats.write_text('"Name","Calls","TotalDurationNs","AverageNs","Percentage","MinNs","MaxNs","StdDev"\n'
+                     + "".join(f'"{n}",10,1,{ms * 1e6},1,{ms * 1e6},{ms * 1e6},0\n' for n, ms in rows))
+    traffic = tmp_path / "traffic.json"
+    traffic.write_text(json.dumps({"kernel_source_hash": kernel_source_hash("fp32"), "prec": "fp32",
+                                   "fetch_scale": 2.0, "write_scale": 1.0,
+                                   "calibration_copy_bytes": 256 << 20, "kernels": {}, "command": "c"}))
+    n, p = 32, 7
+    smin = algorithmic_bytes(p, "fp32")["stage_min"] * n ** 3
+    for fuse, t in ((False, 0.5 + 0.3 + 0.8), (True, 0.3 + 1.4)):
+        text = stage_markdown(str(stats), str(traffic), n, p, "fp32", (1, 2), fuse, "trace")
+        line = [l for l in text.splitlines() if l.startswith("Stage (")][0]
+        parts = ("k_prepass32 + k_face32 + k_volume32" if not fuse else "k_face32 + k_volume32_pre")
+        assert line.startswith(f"Stage ({parts}): {t:.4f} ms"), line
+        assert f"{smin / (t * 1e-3) / 8e12:.3f} of 8 TB/s" in line
