@@ -9,9 +9,9 @@ At t in {0, 1, 5, 10} the run's residual is compared, on a random sample of elem
 oracle's residual of the same state in double and long double (the FP64 run against the floor
 rule of the parity tests; the FP32 form's error is stated).
 
-  python tests/long_ke_dissipation.py --prec fp64 --out gpurun_out/ke_fp64.json
-  python tests/long_ke_dissipation.py --prec fp32 --out gpurun_out/ke_fp32.json
-  python tests/long_ke_dissipation.py --compare gpurun_out/ke_fp64.json gpurun_out/ke_fp32.json
+  python tests/long_ke_dissipation.py --prec fp64 --out ke_fp64.json
+  python tests/long_ke_dissipation.py --prec fp32 --out ke_fp32.json
+  python tests/long_ke_dissipation.py --compare ke_fp64.json ke_fp32.json
 
 The comparison reports max_t |eps_32 - eps_64| / max_t eps_64 over the recorded times.
 """
